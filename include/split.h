@@ -1,0 +1,139 @@
+/*
+ * split.h -- C ABI of the MI355X scenario-batched Split library (libsplitgpu.so).
+ *
+ * The operation (arXiv 2511.18022, Section 3, Eqs. (1)-(3)): a giant tour s_1..s_n is split
+ * into capacity-feasible consecutive routes independently for every demand scenario w.
+ * With f(0) = 0,
+ *     f(i) = min over mask(i) <= p <= i-1 of
+ *            f(p) + c(0, s_{p+1}) + sum_{k=p+1}^{i-1} c(s_k, s_{k+1}) + c(s_i, 0),
+ *     mask(i) = smallest p < i with sum_{k=p+1}^{i} q^w_{s_k} <= Q            (Eq. (2)),
+ * and the scenario's recourse cost is f(n). The expected second-stage cost of the tour is
+ * the mean of f(n) over the scenarios (Section 2, two-stage objective; appendix, sample-
+ * average problem). All cost and DP arithmetic is exact int32; demands are int16.
+ *
+ * Conventions used by every function:
+ *  - Every function returns split_status; nothing throws, aborts, or prints.
+ *  - Node 0 is the depot; customers are 1..N. The return depot of the paper (n+1) is the
+ *    depot's location, so the closing arc of a route ending at customer c is d[c][0].
+ *  - Unlimited fleet, no route-length limit (the paper's "if applicable" limit is not used).
+ *  - A context is not thread-safe: use one context per host thread / stream.
+ *  - Limits: 1 <= n <= N <= SPLIT_MAX_N, 1 <= Q <= 32767, 1 <= S < 2^31.
+ */
+#ifndef SPLIT_H
+#define SPLIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPLIT_MAX_N 8192
+
+typedef enum {
+    SPLIT_OK = 0,
+    SPLIT_E_INVAL = -1,  /* NULL pointer, size out of range, ld < S, no instance set, ... */
+    SPLIT_E_TOUR = -2,   /* a tour id outside 1..N, or repeated */
+    SPLIT_E_DEMAND = -3, /* a scenario has a demand q < 0 or q > Q on the tour: Eq. (2)'s set
+                            is empty, no feasible split exists (detected on the device) */
+    SPLIT_E_RANGE = -4,  /* distances too large: the int32 DP could overflow */
+    SPLIT_E_HIP = -5,    /* a HIP runtime call failed (message in split_last_error) */
+    SPLIT_E_NOMEM = -6   /* device or host allocation failed */
+} split_status;
+
+/* Kernel form used by split_eval (both compute identical results). */
+typedef enum {
+    SPLIT_FORM_AUTO = 0, /* scenario-per-lane for large S, wavefront-per-scenario for small S */
+    SPLIT_FORM_LANE = 1, /* one scenario per lane; sliding-window minimum in LDS */
+    SPLIT_FORM_WAVE = 2  /* one scenario per wavefront; lanes over predecessors p */
+} split_form;
+
+/*
+ * Sample-average statistics of one split_eval call over its S scenarios.
+ *  sum               = sum_s cost[s]                        (exact)
+ *  sumsq_hi:sumsq_lo = sum_s cost[s]^2 as a 128-bit integer  (exact)
+ *  mean = (double)sum / S
+ *  var  = (((double)(S*sumsq - sum^2)) / S) / (S - 1)   sample variance, 0 when S == 1;
+ *         the 128-bit numerator is exact and rounded to double once.
+ *  n_fallback = scenarios whose capacity window outgrew the fast kernel's history and were
+ *         re-evaluated by the general kernel (diagnostic only; results are exact either way).
+ */
+typedef struct {
+    int64_t sum;
+    uint64_t sumsq_lo;
+    uint64_t sumsq_hi;
+    double mean;
+    double var;
+    int64_t n_fallback;
+} split_stats;
+
+typedef struct split_ctx split_ctx;
+
+/* Create a context on HIP device `hip_device`. *out receives the handle (NULL on failure). */
+split_status split_ctx_create(int hip_device, split_ctx **out);
+
+/* Free the context and its device buffers. Waits for the context's outstanding work. NULL ok. */
+void split_ctx_destroy(split_ctx *ctx);
+
+/* Human-readable message for the last failing call on ctx (valid until the next call). */
+const char *split_last_error(const split_ctx *ctx);
+
+/*
+ * Set the instance from integer coordinates. xy: HOST, int32 [(N+1) * 2], node v at
+ * (xy[2v], xy[2v+1]), node 0 the depot; |coordinate| <= 2^20. Distances are the Euclidean
+ * distances rounded to the nearest integer (exact integer square root; halves cannot occur).
+ * Copied; the caller keeps ownership. Errors: SPLIT_E_INVAL.
+ */
+split_status split_instance_set_coords(split_ctx *ctx, int32_t N, const int32_t *xy);
+
+/*
+ * Set the instance from a user distance matrix. d: HOST, int32 [(N+1) * (N+1)], row-major,
+ * d[a*(N+1)+b] = cost of arc a->b (asymmetric allowed), all entries >= 0. Copied.
+ * Errors: SPLIT_E_INVAL (N out of range, negative entry).
+ */
+split_status split_instance_set_dist(split_ctx *ctx, int32_t N, const int32_t *d);
+
+/*
+ * Evaluate one giant tour against S demand scenarios.
+ *  tour   HOST int32 [n]: distinct customer ids in 1..N (a subset of the customers is allowed).
+ *  demand DEVICE int16, N rows of leading dimension ld: demand[(c-1)*ld + s] is customer c's
+ *         demand in scenario s (scenario index fastest). Read only.
+ *  cost   DEVICE int32 [S]: receives f(n) for every scenario. Undefined on SPLIT_E_DEMAND.
+ *  stats  HOST or NULL. Non-NULL: the call blocks until the statistics are on the host.
+ *         NULL: the call only enqueues work on `hip_stream`; split_stats_get() collects the
+ *         statistics (and any device-detected error) of the latest call later.
+ *  hip_stream  hipStream_t to run on (NULL = the default stream).
+ * The library never frees or retains caller pointers; enqueued work reads `demand` and
+ * writes `cost` until the stream reaches it.
+ * Errors: SPLIT_E_INVAL, SPLIT_E_TOUR, SPLIT_E_RANGE (4*(n+1)*max_arc >= 2^31),
+ * SPLIT_E_DEMAND (blocking calls), SPLIT_E_HIP, SPLIT_E_NOMEM.
+ */
+split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const int16_t *demand,
+                        int64_t S, int64_t ld, int32_t Q, int32_t *cost, split_stats *stats,
+                        void *hip_stream);
+
+/*
+ * Wait for the latest split_eval on ctx and return its statistics. Returns SPLIT_E_DEMAND if
+ * that call found an infeasible demand, SPLIT_E_INVAL if no call was made yet.
+ */
+split_status split_stats_get(split_ctx *ctx, split_stats *stats);
+
+/* Choose the kernel form for later split_eval calls (default SPLIT_FORM_AUTO). */
+split_status split_set_form(split_ctx *ctx, int form);
+
+/*
+ * Kernel timing for benchmarks: when enabled, split_eval records HIP events around its
+ * dominant kernel on the caller's stream. split_timing_get waits for the last call and
+ * returns the accumulated dominant-kernel milliseconds and the number of timed launches
+ * since the last reset, with the name of the kernel timed.
+ */
+split_status split_timing_enable(split_ctx *ctx, int enable);
+split_status split_timing_get(split_ctx *ctx, double *ms_total, int64_t *launches,
+                              const char **kernel_name);
+split_status split_timing_reset(split_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLIT_H */
