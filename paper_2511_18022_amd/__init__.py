@@ -1,0 +1,212 @@
+"""MI355X-native scenario-batched Split (arXiv 2511.18022, Section 3).
+
+Thin ctypes binding of ``libsplitgpu.so`` (C ABI in ``include/split.h``). It only marshals
+arguments: every step of the evaluation runs in the library's HIP kernels. PyTorch supplies
+device memory (``torch.Tensor.data_ptr``) and the stream. There is no CPU fallback: if the
+library is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsplitgpu.so")
+
+SPLIT_OK, SPLIT_E_INVAL, SPLIT_E_TOUR, SPLIT_E_DEMAND = 0, -1, -2, -3
+SPLIT_E_RANGE, SPLIT_E_HIP, SPLIT_E_NOMEM = -4, -5, -6
+FORM_AUTO, FORM_LANE, FORM_WAVE = 0, 1, 2
+FORMS = {"auto": FORM_AUTO, "lane": FORM_LANE, "wave": FORM_WAVE}
+STATUS_NAMES = {0: "SPLIT_OK", -1: "SPLIT_E_INVAL", -2: "SPLIT_E_TOUR", -3: "SPLIT_E_DEMAND",
+                -4: "SPLIT_E_RANGE", -5: "SPLIT_E_HIP", -6: "SPLIT_E_NOMEM"}
+
+# Every function declared in include/split.h.
+EXPORTED = [
+    "split_ctx_create", "split_ctx_destroy", "split_last_error", "split_instance_set_coords",
+    "split_instance_set_dist", "split_eval", "split_stats_get", "split_set_form",
+    "split_timing_enable", "split_timing_get", "split_timing_reset",
+]
+
+
+class SplitError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class SplitStatsC(ctypes.Structure):
+    _fields_ = [("sum", ctypes.c_int64), ("sumsq_lo", ctypes.c_uint64),
+                ("sumsq_hi", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("var", ctypes.c_double), ("n_fallback", ctypes.c_int64)]
+
+
+@dataclass
+class SplitStats:
+    sum: int
+    sumsq: int
+    mean: float
+    var: float
+    n_fallback: int
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsplitgpu.so and declare its C signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2511_18022_amd._build` "
+            "(hipcc, gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.split_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.split_ctx_destroy.argtypes = [P]
+    lib.split_ctx_destroy.restype = None
+    lib.split_last_error.argtypes = [P]
+    lib.split_last_error.restype = ctypes.c_char_p
+    lib.split_instance_set_coords.argtypes = [P, i32, P]
+    lib.split_instance_set_dist.argtypes = [P, i32, P]
+    lib.split_eval.argtypes = [P, P, i32, P, i64, i64, i32, P, P, P]
+    lib.split_stats_get.argtypes = [P, ctypes.POINTER(SplitStatsC)]
+    lib.split_set_form.argtypes = [P, ctypes.c_int]
+    lib.split_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.split_timing_get.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_char_p)]
+    lib.split_timing_reset.argtypes = [P]
+    for name in EXPORTED:
+        fn = getattr(lib, name)
+        if name not in ("split_ctx_destroy", "split_last_error"):
+            fn.restype = ctypes.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _np():
+    import numpy as np
+    return np
+
+
+class SplitContext:
+    """One library context (device buffers, instance, timing) bound to a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        st = self._lib.split_ctx_create(int(device), ctypes.byref(h))
+        if st != SPLIT_OK:
+            raise SplitError(st, f"split_ctx_create(device={device}) failed")
+        self._h = h
+        self.device = device
+        self.N = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.split_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int):
+        if st != SPLIT_OK:
+            msg = self._lib.split_last_error(self._h)
+            raise SplitError(st, msg.decode() if msg else "")
+
+    # -- instance
+    def set_coords(self, xy):
+        np = _np()
+        a = np.ascontiguousarray(xy, dtype=np.int32)
+        if a.ndim != 2 or a.shape[1] != 2:
+            raise ValueError("xy must be [(N+1), 2]")
+        self._check(self._lib.split_instance_set_coords(self._h, a.shape[0] - 1,
+                                                        a.ctypes.data_as(ctypes.c_void_p)))
+        self.N = a.shape[0] - 1
+
+    def set_dist(self, d):
+        np = _np()
+        a = np.ascontiguousarray(d, dtype=np.int32)
+        if a.ndim != 2 or a.shape[0] != a.shape[1]:
+            raise ValueError("d must be square [(N+1), (N+1)]")
+        self._check(self._lib.split_instance_set_dist(self._h, a.shape[0] - 1,
+                                                      a.ctypes.data_as(ctypes.c_void_p)))
+        self.N = a.shape[0] - 1
+
+    def set_form(self, form):
+        self._check(self._lib.split_set_form(self._h, FORMS.get(form, form)))
+
+    # -- evaluation
+    def eval(self, tour, demand, Q: int, S: int | None = None, cost=None, sync: bool = True,
+             stream=None):
+        """Split `tour` under every scenario of `demand` (torch.int16 CUDA tensor [N, ld]).
+
+        Returns (cost, SplitStats) when sync, else (cost, None) with the work enqueued.
+        """
+        import torch
+        np = _np()
+        t = np.ascontiguousarray(tour, dtype=np.int32)
+        if not (isinstance(demand, torch.Tensor) and demand.is_cuda and
+                demand.dtype == torch.int16 and demand.dim() == 2 and
+                demand.stride(1) == 1):
+            raise ValueError("demand must be a CUDA int16 tensor [N, ld] with unit column stride")
+        ld = demand.stride(0)
+        S = demand.shape[1] if S is None else int(S)
+        if S > demand.shape[1]:
+            raise ValueError(f"S={S} exceeds the demand tensor's {demand.shape[1]} columns")
+        # ids above N are the library's to reject (SPLIT_E_TOUR)
+        if t.size and demand.shape[0] < int(t.max()) <= self.N:
+            raise ValueError("the demand tensor has fewer rows than the largest tour customer id")
+        if cost is None:
+            cost = torch.empty(max(S, 1), dtype=torch.int32, device=demand.device)
+        elif not (cost.is_cuda and cost.dtype == torch.int32 and cost.is_contiguous() and
+                  cost.numel() >= S):
+            raise ValueError("cost must be a contiguous CUDA int32 tensor with >= S elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(demand.device)
+        sh = ctypes.c_void_p(stream.cuda_stream)
+        out = SplitStatsC()
+        st = self._lib.split_eval(self._h, t.ctypes.data_as(ctypes.c_void_p), len(t),
+                                  ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q),
+                                  ctypes.c_void_p(cost.data_ptr()),
+                                  ctypes.byref(out) if sync else None, sh)
+        self._check(st)
+        return cost, (self._stats(out) if sync else None)
+
+    def stats(self) -> SplitStats:
+        out = SplitStatsC()
+        self._check(self._lib.split_stats_get(self._h, ctypes.byref(out)))
+        return self._stats(out)
+
+    @staticmethod
+    def _stats(c: SplitStatsC) -> SplitStats:
+        return SplitStats(sum=int(c.sum), sumsq=(int(c.sumsq_hi) << 64) | int(c.sumsq_lo),
+                          mean=float(c.mean), var=float(c.var), n_fallback=int(c.n_fallback))
+
+    # -- timing of the dominant kernel
+    def timing(self, enable: bool = True):
+        self._check(self._lib.split_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_reset(self):
+        self._check(self._lib.split_timing_reset(self._h))
+
+    def timing_get(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        name = ctypes.c_char_p()
+        self._check(self._lib.split_timing_get(self._h, ctypes.byref(ms), ctypes.byref(n),
+                                               ctypes.byref(name)))
+        return float(ms.value), int(n.value), (name.value.decode() if name.value else "")

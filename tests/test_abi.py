@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/split.h declares; host-side
+argument checks that need no GPU. CPU only (no kernels are launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2511_18022_amd as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "split.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(split_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sg.LIB_PATH):
+        from paper_2511_18022_amd import _build
+        _build.build()
+    return sg.load_library()
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(sg.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_null_context_is_rejected_without_touching_the_gpu(lib):
+    null = ctypes.c_void_p()
+    assert lib.split_instance_set_coords(null, 5, None) == sg.SPLIT_E_INVAL
+    assert lib.split_instance_set_dist(null, 5, None) == sg.SPLIT_E_INVAL
+    assert lib.split_eval(null, None, 1, None, 1, 1, 1, None, None, None) == sg.SPLIT_E_INVAL
+    assert lib.split_set_form(null, 1) == sg.SPLIT_E_INVAL
+    assert lib.split_timing_enable(null, 1) == sg.SPLIT_E_INVAL
+    assert lib.split_stats_get(null, None) == sg.SPLIT_E_INVAL
+    assert lib.split_ctx_create(0, None) == sg.SPLIT_E_INVAL
+    assert lib.split_last_error(null) == b"null context"
+    lib.split_ctx_destroy(null)
+
+
+def test_status_codes_match_header():
+    text = open(HEADER).read()
+    for name, val in re.findall(r"(SPLIT_E_[A-Z]+|SPLIT_OK)\s*=\s*(-?\d+)", text):
+        assert getattr(sg, name) == int(val), name

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle, bit for bit.
+
+Every cost is an exact integer, so the bar is equality of every scenario's cost, of the
+exact moments, and of the mean and variance doubles (both sides use the same exact
+integers and the same operation order). Inputs are seeded and synthetic (see gen/).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2511_18022_amd as sg
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = sg.SplitContext(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, tour, dem_np, Q, form="auto", S=None, xy=None, d=None, ld=None):
+    if xy is not None:
+        ctx.set_coords(xy)
+    if d is not None:
+        ctx.set_dist(d)
+    ctx.set_form(form)
+    N, S0 = dem_np.shape
+    S = S0 if S is None else S
+    if ld is not None and ld > S0:
+        pad = np.zeros((N, ld), dtype=np.int16)
+        pad[:, :S0] = dem_np
+        dem_np = pad
+    dem = torch.from_numpy(np.ascontiguousarray(dem_np)).cuda()
+    cost, st = ctx.eval(tour, dem, Q, S=S)
+    torch.cuda.synchronize()
+    return cost[:S].cpu().numpy(), st
+
+
+def check_against_oracle(ctx, tour, dem_np, Q, d_oracle, form="auto", xy=None, d=None):
+    got, st = run_gpu(ctx, tour, dem_np, Q, form=form, xy=xy, d=d)
+    want = oracle.split(tour, d_oracle, np.ascontiguousarray(dem_np), Q,
+                        threads=ORACLE_THREADS)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (f"{bad.size} mismatching scenarios, first {bad[:5]}: "
+                           f"gpu {got[bad[:5]]} oracle {want[bad[:5]]}")
+    mom = oracle.moments(want)
+    assert st.sum == mom["sum"] and st.sumsq == mom["sumsq"]
+    assert st.mean == mom["mean"] and st.var == mom["var"]
+    return got, st
+
+
+WORKLOADS_SMALL = ["uniform-n20", "poisson-n200"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS_SMALL)
+@pytest.mark.parametrize("form", ["lane", "wave", "auto"])
+def test_named_workloads_full_size(ctx, name, form):
+    w = gen.make_workload(name)
+    print(f"[parity] {name} S={w.S} form={form}", flush=True)
+    d = oracle.dist_matrix(w.xy)
+    check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form=form, xy=w.xy)
+
+
+def test_copula_n1000_full_size_all_scenarios(ctx):
+    w = gen.make_workload("copula-n1000")
+    print(f"[parity] copula-n1000 S={w.S} form=auto (all scenarios)", flush=True)
+    d = oracle.dist_matrix(w.xy)
+    _, st = check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form="auto", xy=w.xy)
+    print(f"[parity] copula-n1000 fallback scenarios: {st.n_fallback}", flush=True)
+
+
+@pytest.mark.parametrize("S", [1, 2, 63, 64, 65, 1037, 4097])
+@pytest.mark.parametrize("form", ["lane", "wave"])
+def test_ragged_scenario_counts(ctx, S, form):
+    w = gen.make_workload("copula-n1000", S=S)
+    n = 300
+    tour = w.tour[:n]
+    d = oracle.dist_matrix(w.xy)
+    check_against_oracle(ctx, tour, w.demand, 500, d, form=form, xy=w.xy)
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 31, 32, 33, 47, 48, 49, 64, 65, 97])
+def test_short_and_block_boundary_tours(ctx, n):
+    rng = np.random.default_rng(100 + n)
+    N = 120
+    xy = gen.coords(9, N)
+    d = oracle.dist_matrix(xy)
+    tour = rng.permutation(np.arange(1, N + 1))[:n].astype(np.int32)
+    dem = gen.demand_uniform(9, N, 333, 0, 60)
+    for form in ("lane", "wave"):
+        check_against_oracle(ctx, tour, dem, 150, d, form=form, xy=xy)
+
+
+def test_padded_leading_dimension(ctx):
+    w = gen.make_workload("poisson-n200", S=3000)
+    d = oracle.dist_matrix(w.xy)
+    got, _ = run_gpu(ctx, w.tour, w.demand, w.Q, form="lane", xy=w.xy, ld=3000 + 77)
+    want = oracle.split(w.tour, d, w.demand, w.Q, threads=ORACLE_THREADS)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("form", ["lane", "wave"])
+def test_asymmetric_user_matrix_and_subset_tour(ctx, form):
+    rng = np.random.default_rng(7)
+    N = 400
+    dmat = rng.integers(0, 5000, size=(N + 1, N + 1)).astype(np.int32)
+    np.fill_diagonal(dmat, 0)
+    tour = rng.permutation(np.arange(1, N + 1))[:250].astype(np.int32)
+    dem = gen.demand_poisson(5, N, 5000, 2.0, 30.0, 300)
+    check_against_oracle(ctx, tour, dem, 300, dmat, form=form, d=dmat)
+
+
+@pytest.mark.parametrize("form", ["lane", "wave"])
+def test_long_zero_demand_runs_take_the_general_kernel(ctx, form):
+    # windows far longer than the lane kernel's LDS history: the lane kernel must queue these
+    # scenarios for the general kernel and the results must stay exact
+    N = 600
+    xy = gen.coords(11, N)
+    d = oracle.dist_matrix(xy)
+    tour = gen.tour(11, N)
+    dem = gen.demand_uniform(11, N, 2000, 0, 40)
+    rng = np.random.default_rng(3)
+    zero_cols = rng.choice(2000, size=300, replace=False)
+    for c in zero_cols:
+        lo = int(rng.integers(0, N - 200))
+        dem[lo:lo + int(rng.integers(60, 200)), c] = 0
+    dem[:, zero_cols[:20]] = 0  # whole scenarios without demand: one route
+    _, st = check_against_oracle(ctx, tour, dem, 200, d, form=form, xy=xy)
+    if form == "lane":
+        assert st.n_fallback > 0
+
+
+@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("bad", ["over_capacity", "negative"])
+def test_infeasible_demand_is_reported(ctx, form, bad):
+    import paper_2511_18022_amd as sg
+    w = gen.make_workload("uniform-n20", S=500)
+    dem = w.demand.copy()
+    dem[int(w.tour[7]) - 1, 123] = 101 if bad == "over_capacity" else -3
+    ctx.set_coords(w.xy)
+    ctx.set_form(form)
+    with pytest.raises(sg.SplitError) as ei:
+        ctx.eval(w.tour, torch.from_numpy(dem).cuda(), w.Q)
+    assert ei.value.status == sg.SPLIT_E_DEMAND
+    # a demand outside the tour does not matter
+    dem2 = w.demand.copy()
+    sub = w.tour[:10]
+    outside = int(w.tour[15]) - 1
+    dem2[outside, 5] = 101
+    d = oracle.dist_matrix(w.xy)
+    got, _ = run_gpu(ctx, sub, dem2, w.Q, form=form)
+    want = oracle.split(sub, d, dem2, w.Q)
+    assert np.array_equal(got, want)
+
+
+def test_invalid_arguments(ctx):
+    import paper_2511_18022_amd as sg
+    w = gen.make_workload("uniform-n20", S=100)
+    ctx.set_coords(w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    for tour, Q, code in [
+        (np.array([1, 2, 2], dtype=np.int32), 100, sg.SPLIT_E_TOUR),
+        (np.array([0, 2, 3], dtype=np.int32), 100, sg.SPLIT_E_TOUR),
+        (np.array([1, 2, 21], dtype=np.int32), 100, sg.SPLIT_E_TOUR),
+        (w.tour, 0, sg.SPLIT_E_INVAL),
+        (w.tour, 16384, sg.SPLIT_E_INVAL),
+    ]:
+        with pytest.raises(sg.SplitError) as ei:
+            ctx.eval(tour, dem, Q)
+        assert ei.value.status == code
+    big = np.zeros((3, 3), dtype=np.int32)
+    big[0, 1] = big[1, 0] = big[0, 2] = big[2, 0] = big[1, 2] = big[2, 1] = 300_000_000
+    ctx.set_dist(big)
+    with pytest.raises(sg.SplitError) as ei:
+        ctx.eval(np.array([1, 2], dtype=np.int32), dem, 100)
+    assert ei.value.status == sg.SPLIT_E_RANGE
+
+
+def test_maximum_capacity_and_run_twice_determinism(ctx):
+    w = gen.make_workload("copula-n1000", S=20000)
+    d = oracle.dist_matrix(w.xy)
+    a, _ = check_against_oracle(ctx, w.tour, w.demand, 16383, d, form="lane", xy=w.xy)
+    b, _ = run_gpu(ctx, w.tour, w.demand, 16383, form="lane", xy=w.xy)
+    assert np.array_equal(a, b)
+    # small capacity (windows of a few customers): demands clipped to Q to stay feasible
+    dem60 = np.ascontiguousarray(np.minimum(w.demand, 60))
+    c, _ = check_against_oracle(ctx, w.tour, dem60, 60, d, form="lane", xy=w.xy)
+    c2, _ = run_gpu(ctx, w.tour, dem60, 60, form="wave", xy=w.xy)
+    assert np.array_equal(c, c2)
+
+
+def test_async_calls_and_stats_get(ctx):
+    w = gen.make_workload("poisson-n200", S=10000)
+    d = oracle.dist_matrix(w.xy)
+    ctx.set_coords(w.xy)
+    ctx.set_form("lane")
+    dem = torch.from_numpy(w.demand).cuda()
+    outs = []
+    for k in range(3):
+        tour = np.ascontiguousarray(np.roll(w.tour, 17 * k))
+        cost, none = ctx.eval(tour, dem, w.Q, sync=False)
+        assert none is None
+        outs.append((tour, cost))
+    st = ctx.stats()
+    for tour, cost in outs:
+        want = oracle.split(tour, d, w.demand, w.Q, threads=ORACLE_THREADS)
+        assert np.array_equal(cost.cpu().numpy(), want)
+    mom = oracle.moments(want)
+    assert st.sum == mom["sum"] and st.var == mom["var"]
