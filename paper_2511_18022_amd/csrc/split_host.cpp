@@ -135,7 +135,7 @@ split_status ensure_capacity(split_ctx *ctx, int32_t n, int64_t S)
         ctx->d_w = nullptr;
         ctx->cap_n = 0;
         if (hipMalloc(&ctx->d_tour, sizeof(int32_t) * nn) != hipSuccess ||
-            hipMalloc(&ctx->d_rowoff, sizeof(int64_t) * (nn + 1)) != hipSuccess ||
+            hipMalloc(&ctx->d_rowoff, sizeof(int64_t) * (nn + 1 + kRowPad)) != hipSuccess ||
             hipMalloc(&ctx->d_w, sizeof(int32_t) * (nn + 1)) != hipSuccess)
             return fail(ctx, SPLIT_E_NOMEM, "device allocation for n=%d failed", nn);
         for (int k = 0; k < kStages; ++k) {
@@ -338,8 +338,10 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
     if (S < 1 || S > INT32_MAX || ld < S)
         return fail(ctx, SPLIT_E_INVAL, "split_eval: need 1 <= S < 2^31 and ld >= S");
     if (Q < 1 || Q > 16383) return fail(ctx, SPLIT_E_INVAL, "split_eval: need 1 <= Q <= 16383");
+    int32_t max_id = 0;
     for (int32_t k = 0; k < n; ++k) {
         const int32_t c = tour[k];
+        max_id = c > max_id ? c : max_id;
         if (c < 1 || c > ctx->N || ctx->seen[c]) {
             for (int32_t j = 0; j < k; ++j) ctx->seen[tour[j]] = 0;
             return fail(ctx, SPLIT_E_TOUR, "split_eval: tour[%d]=%d is out of range or repeated",
@@ -395,6 +397,9 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
 
     int form = ctx->form;
     if (form == SPLIT_FORM_AUTO) form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
+    // The lane kernel addresses demands with 32-bit buffer offsets.
+    const bool lane_addressable = ((__int128)(max_id - 1) * ld + S) * 2 < ((__int128)1 << 32);
+    if (form == SPLIT_FORM_LANE && !lane_addressable) form = SPLIT_FORM_WAVE;
     hipEvent_t stop = nullptr;
     st = timing_begin(ctx, stream, &stop);
     if (st != SPLIT_OK) return st;

@@ -23,11 +23,15 @@ struct DevStats {
 //   w[0]   = c(0, s_1)                                    (g_0 = f_0 + a_0)
 //   w[i]   = c(s_i, 0) + c(0, s_{i+1}) - c(s_i, s_{i+1})   1 <= i <= n-1
 //   w[n]   = D[n] + c(s_n, 0)                             (turns g back into f at i = n)
-//   rowoff[i] = (s_i - 1) * ld   (element offset of position i's demand row), 1 <= i <= n
+//   rowoff[i] = (s_i - 1) * ld * 2   (byte offset of position i's int16 demand row), 1 <= i <= n
 // With g_p = f_p + c(0, s_{p+1}) - D[p+1] (D[k] = tour arc sum up to position k), Eq. (3)
 // becomes g_i = w_i + min_{p in window(i)} g_p, and f_n = w_n + min_{p in window(n)} g_p.
+// rowoff entries past position n that the prep kernel fills with a valid row (kernels load
+// whole blocks of positions without per-position guards).
+constexpr int kRowPad = 64;
+
 struct TourDev {
-    int64_t *rowoff;  // [n + 1]
+    int64_t *rowoff;  // [n + 1 + kRowPad]
     int32_t *w;       // [n + 1]
 };
 

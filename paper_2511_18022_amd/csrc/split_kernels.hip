@@ -56,7 +56,7 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
     long long link_sum = 0;
     for (int k = tid + 1; k <= n; k += 1024) {
         const int sk = a.tour[k - 1];
-        a.out.rowoff[k] = (long long)(sk - 1) * a.ld;
+        a.out.rowoff[k] = (long long)(sk - 1) * a.ld * (long long)sizeof(uint16_t);
         if (k < n) {
             const int sn = a.tour[k];
             const int link = arc_cost(a, sk, sn);
@@ -70,6 +70,8 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
         if (tid < off) red[tid] += red[tid + off];
         __syncthreads();
     }
+    // positions n+1 .. n+kRowPad read row 0 (valid memory): lets kernels load whole blocks
+    for (int k = n + 1 + tid; k <= n + kRowPad; k += 1024) a.out.rowoff[k] = 0;
     if (tid == 0) {
         a.out.rowoff[0] = 0;
         a.out.w[0] = arc_cost(a, 0, a.tour[0]);
@@ -84,116 +86,271 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 
 // ------------------------------------------------------------------------- lane kernel
 //
-// One lane = one scenario; a workgroup is one wavefront of 64 scenarios. Per lane, LDS holds
-// (lane-interleaved, so any per-lane index is bank-conflict free):
-//   pp  : prefix loads P_p mod 2^16 of the last 64 positions (two positions per dword),
-//   suf : for the last 4 blocks of 16 positions, suffix minima of g inside each block,
-//   bsf : per block b, the minimum of the block minima strictly between b and the current
-//         block.
-// For state i with window [s, i-1] and current block c (the block of position i-1):
-//   s in an older block:  min g = min(suf[s], bsf[block(s)], running minimum of block c);
-//   s in block c:         the window lies in the current block, whose g are in registers.
-// The window start s advances as a two-pointer on the prefix loads (Eq. (2)); the 16-bit
-// comparison is exact because every compared difference lies in [-Q, Q] and Q < 2^14.
+// One lane = one scenario; a workgroup is one wavefront of 64 scenarios. Positions are
+// processed in blocks of kLB = 16. Per lane, LDS holds (lane-interleaved, so a per-lane
+// index never causes a bank conflict):
+//   pp : prefix loads P_p mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword k;
+//        dwords 0..2 are mirrored after the ring so a 4-dword read never wraps;
+//   sf : for the last 4 blocks, the suffix minimum of g inside each block;
+//   bs : per block b, the minimum of the block minima strictly between b and the current
+//        block.
+// For state i with window [s, i-1] whose newest position i-1 lies in block c:
+//   s in an older block:  min g = min(sf[s], bs[block(s)], running minimum of block c),
+//   s in block c:         the window lies in block c, whose g values are in registers.
+// Window starts (Eq. (2)) come from the prefix loads: s_i = s_{i-1} + #{p >= s_{i-1} :
+// P_p < P_i - Q}. The count reads 8 positions at once and compares them as packed 16-bit
+// differences; it is exact because every compared difference lies in [-Q - q_i, Q] with
+// Q < 2^14 and q_i < 2^15 (bit 15 of a demand is checked separately). A lane whose 8th
+// position also expired, or whose 8 positions reach past the last written prefix, redoes the
+// block with a one-position-at-a-time loop.
+// The window starts of block b+1 are computed before the DP of block b, so the chain of LDS
+// reads behind them overlaps the DP's arithmetic; demands are loaded two blocks ahead.
 
-constexpr int kLB = 16;      // positions per block
-constexpr int kRing = 64;    // positions of history in LDS (4 blocks)
-constexpr int kWinMax = 48;  // longest window the lane kernel answers itself
+constexpr int kLB = 16;            // positions per block
+constexpr int kRingPairs = 32;     // ring of 64 positions, two per dword
+constexpr int kMirror = 3;         // dwords mirrored after the ring
+constexpr int kStartWinMax = 46;   // longest window at a block start the lane kernel keeps
 
-__global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
+struct LaneLds {
+    uint32_t pp[kRingPairs + kMirror][64];
+    int32_t sf[4 * kLB][64];
+    int32_t bs[4][64];
+};
+
+// Packed 16-bit a - t in both halves (no borrow between the halves).
+__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t t)
 {
-    __shared__ uint32_t pp[kRing / 2][64];
-    __shared__ int32_t suf[kRing][64];
-    __shared__ int32_t bsf[4][64];
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    const u16x2 av = __builtin_bit_cast(u16x2, a);
+    const u16x2 tv = {(unsigned short)t, (unsigned short)t};
+    return __builtin_bit_cast(uint32_t, av - tv);
+}
 
+__device__ __forceinline__ void pp_write(LaneLds &L, int lane, int pos, uint32_t P)
+{
+    uint16_t *h = reinterpret_cast<uint16_t *>(&L.pp[0][0]);
+    const int pr = (pos >> 1) & (kRingPairs - 1);
+    h[(pr * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
+    if (pr < kMirror) h[((pr + kRingPairs) * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
+}
+
+__device__ __forceinline__ bool pp_expired(LaneLds &L, int lane, int pos, uint32_t T)
+{
+    const uint16_t *h = reinterpret_cast<const uint16_t *>(&L.pp[0][0]);
+    const int pr = (pos >> 1) & (kRingPairs - 1);
+    return (int16_t)(uint16_t)(h[(pr * 64 + lane) * 2 + (pos & 1)] - (uint16_t)T) < 0;
+}
+
+// Window starts of the states 16*blk + 1 .. 16*blk + 16 (those <= n).
+// In: s8 = 8 * (window start of state 16*blk), P = prefix load through position 16*blk,
+// q = demands of the block's states. Out: sA[t] = 8 * window start of state 16*blk + t + 1.
+// kFull: all 16 states exist (no per-state guards).
+template <bool kFull>
+__device__ __forceinline__ void lane_phase_a_impl(LaneLds &L, int lane, int blk, int n, int Q,
+                                                  const uint32_t (&q)[kLB], int &P, int &s8,
+                                                  uint32_t &qor, int (&sA)[kLB], bool &ovf)
+{
+    const int first = blk * kLB + 1;
+    const int last = kFull ? first + kLB - 1 : min(first + kLB - 1, n);
+    ovf |= s8 < 8 * (first - 1 - kStartWinMax);
+    int Pt[kLB];
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+        if (!kFull && first + t > n) continue;
+        P += q[t];
+        qor |= q[t];
+        Pt[t] = P;
+        pp_write(L, lane, first + t, (uint32_t)P);
+    }
+    uint32_t sat = 0;  // sign bit: some state's 8th looked-ahead position expired too
+    int last_base8 = s8 & ~15;
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+        if (!kFull && first + t > n) continue;
+        const int prev8 = (t == 0) ? s8 : sA[t - 1];
+        const uint32_t T = (uint32_t)(Pt[t] - Q);
+        const int base8 = prev8 & ~15;
+        const int pr = (prev8 >> 4) & (kRingPairs - 1);
+        const uint32_t d0 = L.pp[pr][lane], d1 = L.pp[pr + 1][lane];
+        const uint32_t d2 = L.pp[pr + 2][lane], d3 = L.pp[pr + 3][lane];
+        const uint32_t m01 = __builtin_amdgcn_perm(pk_sub16(d1, T), pk_sub16(d0, T), 0x0b0a0908u);
+        const uint32_t m23 = __builtin_amdgcn_perm(pk_sub16(d3, T), pk_sub16(d2, T), 0x0b0a0908u);
+        sA[t] = __builtin_popcount(m23) + (__builtin_popcount(m01) + base8);
+        sat |= m23;
+        last_base8 = base8;
+    }
+    // Redo the block one position at a time if a lookahead saturated, or if one reached past
+    // the last written prefix (bases only grow, so the last one decides).
+    const bool rare = (int32_t)sat < 0 || last_base8 > 8 * (last - 7);
+    if (rare && !ovf) {
+        int s = s8 >> 3;
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) {
+            if (!kFull && first + t > n) continue;
+            const uint32_t T = (uint32_t)(Pt[t] - Q);
+            while (pp_expired(L, lane, s, T)) ++s;
+            sA[t] = 8 * s;
+        }
+    }
+    s8 = sA[kFull ? kLB - 1 : (last - first)];
+}
+
+__device__ __forceinline__ void lane_phase_a(LaneLds &L, int lane, int blk, int n, int Q,
+                                             const uint32_t (&q)[kLB], int &P, int &s8,
+                                             uint32_t &qor, int (&sA)[kLB], bool &ovf)
+{
+    if ((blk + 1) * kLB <= n)
+        lane_phase_a_impl<true>(L, lane, blk, n, Q, q, P, s8, qor, sA, ovf);
+    else
+        lane_phase_a_impl<false>(L, lane, blk, n, Q, q, P, s8, qor, sA, ovf);
+}
+
+// DP of the positions p = 16*blk .. 16*blk + 15 (< n): g_p from the previous state's window
+// minimum m, then the window minimum of state p + 1 into m.
+__device__ __forceinline__ void lane_phase_b(LaneLds &L, int lane, int blk, int n,
+                                             const int32_t *__restrict__ w, const int (&sA)[kLB],
+                                             int &m, int &pre, int (&gb)[kLB], bool &err)
+{
+    const int p0 = blk * kLB;
+    const bool full = p0 + kLB <= n;
+    const bool careful = !full || sA[kLB - 1] >= 8 * p0;
+    if (!__any(careful)) {
+        int v1[kLB], v2[kLB];
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) {
+            v1[t] = L.sf[(sA[t] >> 3) & (4 * kLB - 1)][lane];
+            v2[t] = L.bs[(sA[t] >> 7) & 3][lane];
+        }
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) {
+            const int g = m + w[p0 + t];
+            gb[t] = g;
+            pre = (t == 0) ? g : min(pre, g);
+            m = min(min(v1[t], v2[t]), pre);
+        }
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+        const int p = p0 + t;
+        if (p >= n) continue;
+        const int g = (p == 0) ? w[0] : m + w[p];
+        gb[t] = g;
+        pre = (t == 0) ? g : min(pre, g);
+        const int s = sA[t] >> 3;
+        if (s >= p0) {
+            err |= (s == p + 1);
+            int mm = kInf;
+#pragma unroll
+            for (int j = 0; j <= t; ++j)
+                if (p0 + j >= s) mm = min(mm, gb[j]);
+            m = mm;
+        } else {
+            m = min(min(L.sf[s & (4 * kLB - 1)][lane], L.bs[(s >> 4) & 3][lane]), pre);
+        }
+    }
+}
+
+// Suffix minima of block blk into sf, and the between-block minima into bs.
+__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, int blk, const int (&gb)[kLB])
+{
+    const int p0 = blk * kLB;
+    int sm = gb[kLB - 1];
+    L.sf[(p0 + kLB - 1) & (4 * kLB - 1)][lane] = sm;
+#pragma unroll
+    for (int t = kLB - 2; t >= 0; --t) {
+        sm = min(sm, gb[t]);
+        L.sf[(p0 + t) & (4 * kLB - 1)][lane] = sm;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L.bs[j][lane] = min(L.bs[j][lane], sm);
+    L.bs[blk & 3][lane] = kInf;
+}
+
+// Demands of the states of block blk, by buffer loads: the descriptor holds the demand base,
+// the row's byte offset is the scalar offset and the lane's scenario offset the vector one,
+// so no vector instruction goes into addressing. Needs N * ld * 2 < 2^32 (host-checked).
+__device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
+                                                const int64_t *__restrict__ rowoff,
+                                                uint32_t lane_off, int blk, uint32_t (&q)[kLB])
+{
+    // rowoff is padded past n with a valid row, so the last block loads unguarded too
+#pragma unroll
+    for (int t = 0; t < kLB; ++t)
+        q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t + 1], 0);
+}
+
+// One block step: window starts of block blk + 1, DP of block blk, demands of block blk + 2.
+__device__ __forceinline__ void lane_step(LaneLds &L, int lane, int blk, int nblk, int n, int Q,
+                                          __amdgpu_buffer_rsrc_t dem,
+                                          const int64_t *__restrict__ rowoff, uint32_t lane_off,
+                                          const int32_t *__restrict__ w, uint32_t (&qUse)[kLB],
+                                          uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
+                                          int (&sNext)[kLB], int &P, int &s8, uint32_t &qor,
+                                          int &m, int &pre, bool &err, bool &ovf)
+{
+    // unconditional (rows past n are padding): keeps the load queue's wait counts exact
+    lane_load_block(dem, rowoff, lane_off, blk + 2, qLoad);
+    if (blk + 1 < nblk) lane_phase_a(L, lane, blk + 1, n, Q, qUse, P, s8, qor, sNext, ovf);
+    int gb[kLB];
+    lane_phase_b(L, lane, blk, n, w, sCur, m, pre, gb, err);
+    if (blk + 1 < nblk) lane_block_end(L, lane, blk, gb);
+}
+
+// rowoff[i] here is the BYTE offset of position i's demand row.
+__global__ __launch_bounds__(64) void split_lane_kernel(
+    const char *__restrict__ dem_ptr, const int64_t *__restrict__ rowoff,
+    const int32_t *__restrict__ w, int32_t *__restrict__ cost, DevStats *__restrict__ stats,
+    int32_t *__restrict__ ovf_list, long long S, int n, int Q)
+{
+    __shared__ LaneLds L;
     const int lane = threadIdx.x;
     const long long scen_raw = (long long)blockIdx.x * 64 + lane;
-    const bool active = scen_raw < a.S;
-    const long long scen = active ? scen_raw : a.S - 1;
-    const uint16_t *col = a.demand + scen;
-    const int64_t *rowoff = a.tour.rowoff;
-    const int32_t *w = a.tour.w;
-    const int n = a.n;
-    const int Q = a.Q;
+    const bool active = scen_raw < S;
+    const long long scen = active ? scen_raw : S - 1;
+    const uint32_t lane_off = (uint32_t)scen * 2u;
+    // raw buffer over the whole demand matrix (gfx9 descriptor word 3: 0x00020000)
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)dem_ptr, (short)0, -1, 0x00020000);
 
-    uint16_t *pp16 = reinterpret_cast<uint16_t *>(&pp[0][0]);
-    auto pidx = [&](int pos) { return (((pos >> 1) & (kRing / 2 - 1)) * 64 + lane) * 2 + (pos & 1); };
-
-    pp16[pidx(0)] = 0;
+    pp_write(L, lane, 0, 0u);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bsf[j][lane] = kInf;
+    for (int j = 0; j < 4; ++j) L.bs[j][lane] = kInf;
 
-    int P = 0, s = 0, m = 0, pre = kInf;
+    int P = 0, s8 = 0, m = 0, pre = kInf;
     bool err = false, ovf = false;
     // OR of the raw 16-bit demands: bit 15 marks a negative int16 demand, which the 16-bit
     // window test cannot see (it wraps); demands in (Q, 2^15) empty the window instead.
     uint32_t qor = 0;
 
-    uint16_t qc[kLB];
-#pragma unroll
-    for (int t = 0; t < kLB; ++t) qc[t] = (t + 1 <= n) ? col[rowoff[t + 1]] : (uint16_t)0;
-
     const int nblk = (n + kLB - 1) / kLB;
-    for (int cb = 0; cb < nblk; ++cb) {
-        const int cbase = cb * kLB;
-        uint16_t qn[kLB];
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-            const int i = cbase + kLB + t + 1;
-            qn[t] = (i <= n) ? col[rowoff[i]] : (uint16_t)0;
-        }
-        int gb[kLB];
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-            const int p = cbase + t;
-            if (p >= n) continue;
-            const int g = (p == 0) ? w[0] : m + w[p];
-            gb[t] = g;
-            pre = (t == 0) ? g : min(pre, g);
-            // state i = p + 1
-            const int i = p + 1;
-            P += qc[t];
-            qor |= qc[t];
-            pp16[pidx(i)] = (uint16_t)P;
-            const uint16_t T = (uint16_t)(P - Q);
-            while ((int16_t)(uint16_t)(pp16[pidx(s)] - T) < 0) ++s;
-            ovf |= (i - s) > kWinMax;
-            if (s >= cbase) {
-                err |= (s == i);
-                int mm = kInf;
-#pragma unroll
-                for (int j = 0; j <= t; ++j)
-                    if (cbase + j >= s) mm = min(mm, gb[j]);
-                m = mm;
-            } else {
-                m = min(min(suf[s & (kRing - 1)][lane], bsf[(s >> 4) & 3][lane]), pre);
-            }
-        }
-        if (cb + 1 < nblk) {
-            int sm = gb[kLB - 1];
-            suf[(cbase + kLB - 1) & (kRing - 1)][lane] = sm;
-#pragma unroll
-            for (int t = kLB - 2; t >= 0; --t) {
-                sm = min(sm, gb[t]);
-                suf[(cbase + t) & (kRing - 1)][lane] = sm;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bsf[j][lane] = min(bsf[j][lane], sm);
-            bsf[cb & 3][lane] = kInf;
-        }
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) qc[t] = qn[t];
+    uint32_t q0[kLB], q1[kLB];
+    int s0[kLB], s1[kLB];
+    lane_load_block(rsrc, rowoff, lane_off, 0, q0);
+    lane_load_block(rsrc, rowoff, lane_off, 1, q1);
+    lane_phase_a(L, lane, 0, n, Q, q0, P, s8, qor, s0, ovf);
+    // blocks alternate the roles of (q0, q1) and (s0, s1); the loop body has no conditional
+    // step so the compiler's load-wait counts stay exact across iterations
+    int blk = 0;
+    for (; blk + 1 < nblk; blk += 2) {
+        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, s8, qor,
+                  m, pre, err, ovf);
+        lane_step(L, lane, blk + 1, nblk, n, Q, rsrc, rowoff, lane_off, w, q0, q1, s1, s0, P, s8,
+                  qor, m, pre, err, ovf);
     }
+    if (blk < nblk)
+        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, s8, qor,
+                  m, pre, err, ovf);
 
     err |= (qor & 0x8000u) != 0;
     if (active) {
         if (ovf) {
-            const int k = atomicAdd(&a.stats->ovf_count, 1);
-            a.ovf_list[k] = (int32_t)scen;
+            const int k = atomicAdd(&stats->ovf_count, 1);
+            ovf_list[k] = (int32_t)scen;
         } else if (err) {
-            atomicOr(&a.stats->err_demand, 1);
+            atomicOr(&stats->err_demand, 1);
         } else {
-            a.cost[scen] = m + w[n];
+            cost[scen] = m + w[n];
         }
     }
 }
@@ -213,22 +370,48 @@ __device__ __forceinline__ int wave_min(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// One scenario by one wavefront: the window's g values sit in LDS, lane j reads predecessor
-// s + j (+ 64k for long windows), and the wavefront reduces them. Every lane runs the same
-// two-pointer on the same data, so control flow stays uniform.
+// Exclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_exclusive_sum(int v)
+{
+    const int lane = threadIdx.x;
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    return inc - v;
+}
+
+// One scenario by one wavefront. First the prefix loads P_0..P_n are built in LDS with all
+// lanes loading demands in parallel (chunk per lane + wavefront scan). Then, state by state,
+// every lane runs the same two-pointer on the same data (uniform control flow), lane j reads
+// g of predecessor s + j (+ 64k for long windows) and the wavefront reduces them.
 __device__ void wave_one(const EvalArgs &a, long long scen, int32_t *G, int32_t *PP)
 {
     const int lane = threadIdx.x;
     const int n = a.n;
     const int Q = a.Q;
-    const uint16_t *col = a.demand + scen;
-    G[0] = a.tour.w[0];
-    PP[0] = 0;
-    int P = 0, s = 0;
+    const char *dem = reinterpret_cast<const char *>(a.demand + scen);
+    const int chunk = (n + 63) / 64;
+    const int lo = lane * chunk + 1;
+    const int hi = min(lo + chunk - 1, n);
+    int local = 0;
+    for (int i = lo; i <= hi; ++i) local += *(const uint16_t *)(dem + a.tour.rowoff[i]);
+    int run = wave_exclusive_sum(local);
+    for (int i = lo; i <= hi; ++i) {
+        run += *(const uint16_t *)(dem + a.tour.rowoff[i]);
+        PP[i] = run;
+    }
+    if (lane == 0) {
+        PP[0] = 0;
+        G[0] = a.tour.w[0];
+    }
+    __syncthreads();
+    int s = 0;
     bool err = false;
     for (int i = 1; i <= n; ++i) {
-        P += col[a.tour.rowoff[i]];
-        PP[i] = P;
+        const int P = PP[i];
         while (P - PP[s] > Q) ++s;
         if (s == i) {
             err = true;
@@ -341,7 +524,9 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t stream)
 hipError_t launch_lane(const EvalArgs &a, hipStream_t stream)
 {
     const long long nb = (a.S + 63) / 64;
-    hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)nb), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)nb), dim3(64), 0, stream,
+                       reinterpret_cast<const char *>(a.demand), a.tour.rowoff, a.tour.w, a.cost,
+                       a.stats, a.ovf_list, (long long)a.S, a.n, a.Q);
     return hipGetLastError();
 }
 
