@@ -88,34 +88,67 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 //
 // One lane = one scenario; a workgroup is one wavefront of 64 scenarios. Positions are
 // processed in blocks of kLB = 16. Per lane, LDS holds (lane-interleaved, so a per-lane
-// index never causes a bank conflict):
-//   pp : prefix loads P_p mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword k;
-//        dwords 0..2 are mirrored after the ring so a 4-dword read never wraps;
-//   sf : for the last 4 blocks, the suffix minimum of g inside each block;
-//   bs : per block b, the minimum of the block minima strictly between b and the current
-//        block.
+// index costs at most a two-way bank conflict):
+//   pp  : prefix loads P_p mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword k;
+//         the first kMirror dwords are repeated after the ring so a 6-dword read never wraps;
+//   dl  : for the last 4 blocks, the suffix minimum of g inside the block, stored as a 16-bit
+//         offset from the block's minimum;
+//   rec : per block b of the last 4, (minimum of g over b, minimum of the block minima
+//         strictly between b and the current block).
 // For state i with window [s, i-1] whose newest position i-1 lies in block c:
-//   s in an older block:  min g = min(sf[s], bs[block(s)], running minimum of block c),
-//   s in block c:         the window lies in block c, whose g values are in registers.
+//   s in an older block b:  min g = min(bm[b] + dl[s], between[b], running minimum of c),
+//   s in block c:           the window lies in block c, whose g values are in registers.
 // Window starts (Eq. (2)) come from the prefix loads: s_i = s_{i-1} + #{p >= s_{i-1} :
-// P_p < P_i - Q}. The count reads 8 positions at once and compares them as packed 16-bit
+// P_p < P_i - Q}. The count compares 8 (or 12) positions at once as packed 16-bit
 // differences; it is exact because every compared difference lies in [-Q - q_i, Q] with
-// Q < 2^14 and q_i < 2^15 (bit 15 of a demand is checked separately). A lane whose 8th
-// position also expired, or whose 8 positions reach past the last written prefix, redoes the
-// block with a one-position-at-a-time loop.
-// The window starts of block b+1 are computed before the DP of block b, so the chain of LDS
-// reads behind them overlaps the DP's arithmetic; demands are loaded two blocks ahead.
+// Q < 2^14 and q_i < 2^15 (bit 15 of a demand is checked separately). Lanes whose last
+// looked-ahead position expired too, or whose lookahead reached past the written prefixes,
+// redo the block one position at a time. Scenarios whose windows outgrow the 64-position
+// history, or whose suffix-minimum offsets outgrow 16 bits, are queued for the general kernel.
+// A window start s is carried as S = (s << 7) | (lane << 1), which makes the dl offset, the
+// pp row and the even base below s one instruction each.
 
 constexpr int kLB = 16;            // positions per block
 constexpr int kRingPairs = 32;     // ring of 64 positions, two per dword
-constexpr int kMirror = 3;         // dwords mirrored after the ring
+constexpr int kMirror = 5;         // dwords mirrored after the ring
 constexpr int kStartWinMax = 46;   // longest window at a block start the lane kernel keeps
 
 struct LaneLds {
     uint32_t pp[kRingPairs + kMirror][64];
-    int32_t sf[4 * kLB][64];
-    int32_t bs[4][64];
+    uint16_t dl[4 * kLB][64];
+    int32_t rec[4][64][2];
 };
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) volatile uint16_t lds_u16v;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+typedef __attribute__((address_space(3))) char lds_char;
+
+__device__ __forceinline__ int s_of(int S) { return S >> 7; }
+__device__ __forceinline__ int S_of(int s, int lane) { return (s << 7) | (lane << 1); }
+
+__device__ __forceinline__ uint32_t lds_dl_at(LaneLds &L, int S)
+{
+    return *(lds_u16 *)((lds_char *)(&L.dl[0][0]) + (S & 0x1FFE));
+}
+// (block minimum, between-block minimum) of the block holding s
+__device__ __forceinline__ void lds_rec_at(LaneLds &L, int S, uint32_t lane8, int &bm, int &bs)
+{
+    const lds_i32 *r = (const lds_i32 *)((lds_char *)(&L.rec[0][0][0]) +
+                                         (((uint32_t)(S >> 2) & 0x600u) | lane8));
+    bm = r[0];
+    bs = r[1];
+}
+// byte offset of pp row (s >> 1) & 31 for this lane
+__device__ __forceinline__ uint32_t pp_row_off(int S, uint32_t lane4)
+{
+    return ((uint32_t)S & 0x1F00u) | lane4;
+}
+__device__ __forceinline__ uint32_t lds_pp_at(LaneLds &L, uint32_t off, int row)
+{
+    return *(lds_u32 *)((lds_char *)(&L.pp[0][0]) + off + row * 256);
+}
 
 // Packed 16-bit a - t in both halves (no borrow between the halves).
 __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t t)
@@ -126,9 +159,23 @@ __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t t)
     return __builtin_bit_cast(uint32_t, av - tv);
 }
 
+// Bytes 0..3 = 0xFF where the matching 16-bit half of (lo.lo, lo.hi, hi.lo, hi.hi) is negative.
+__device__ __forceinline__ uint32_t sign_bytes(uint32_t hi, uint32_t lo)
+{
+    return __builtin_amdgcn_perm(hi, lo, 0x0b0a0908u);
+}
+
+// Window start after counting expired positions from the even position below S_prev:
+// cnt8 = 8 * (number of expired positions among those read).
+__device__ __forceinline__ int start_from(int S_prev, uint32_t cnt8)
+{
+    return (int)(cnt8 << 4) + (S_prev & ~0x80);
+}
+
+// 16-bit stores, one per position: kept unmerged so no instruction packs two positions.
 __device__ __forceinline__ void pp_write(LaneLds &L, int lane, int pos, uint32_t P)
 {
-    uint16_t *h = reinterpret_cast<uint16_t *>(&L.pp[0][0]);
+    lds_u16v *h = (lds_u16v *)(&L.pp[0][0]);
     const int pr = (pos >> 1) & (kRingPairs - 1);
     h[(pr * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
     if (pr < kMirror) h[((pr + kRingPairs) * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
@@ -141,19 +188,12 @@ __device__ __forceinline__ bool pp_expired(LaneLds &L, int lane, int pos, uint32
     return (int16_t)(uint16_t)(h[(pr * 64 + lane) * 2 + (pos & 1)] - (uint16_t)T) < 0;
 }
 
-// Window starts of the states 16*blk + 1 .. 16*blk + 16 (those <= n).
-// In: s8 = 8 * (window start of state 16*blk), P = prefix load through position 16*blk,
-// q = demands of the block's states. Out: sA[t] = 8 * window start of state 16*blk + t + 1.
-// kFull: all 16 states exist (no per-state guards).
+// Prefix loads of the states first .. first + 15 into the ring and Pt.
 template <bool kFull>
-__device__ __forceinline__ void lane_phase_a_impl(LaneLds &L, int lane, int blk, int n, int Q,
-                                                  const uint32_t (&q)[kLB], int &P, int &s8,
-                                                  uint32_t &qor, int (&sA)[kLB], bool &ovf)
+__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, int first, int n,
+                                            const uint32_t (&q)[kLB], int &P, uint32_t &qor,
+                                            int (&Pt)[kLB])
 {
-    const int first = blk * kLB + 1;
-    const int last = kFull ? first + kLB - 1 : min(first + kLB - 1, n);
-    ovf |= s8 < 8 * (first - 1 - kStartWinMax);
-    int Pt[kLB];
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
         if (!kFull && first + t > n) continue;
@@ -162,74 +202,105 @@ __device__ __forceinline__ void lane_phase_a_impl(LaneLds &L, int lane, int blk,
         Pt[t] = P;
         pp_write(L, lane, first + t, (uint32_t)P);
     }
-    uint32_t sat = 0;  // sign bit: some state's 8th looked-ahead position expired too
-    int last_base8 = s8 & ~15;
+}
+
+// Exact one-position-at-a-time window starts for states first .. last (the rare path).
+__device__ __forceinline__ void lane_starts_exact(LaneLds &L, int lane, int first, int last,
+                                                  int Q, int S_start, const int (&Pt)[kLB],
+                                                  int (&sA)[kLB])
+{
+    int s = s_of(S_start);
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+        if (first + t > last) continue;
+        const uint32_t T = (uint32_t)(Pt[t] - Q);
+        while (pp_expired(L, lane, s, T)) ++s;
+        sA[t] = S_of(s, lane);
+    }
+}
+
+// Window starts of the states 16*blk + 1 .. 16*blk + 16 (those <= n), one state at a time
+// with an 8-position lookahead. Used for the first and the last block.
+// In: S = start of state 16*blk. Out: sA[t] = start of state 16*blk + t + 1; S = the last.
+template <bool kFull>
+__device__ __forceinline__ void lane_phase_a_impl(LaneLds &L, int lane, int blk, int n, int Q,
+                                                  const uint32_t (&q)[kLB], int &P, int &S,
+                                                  uint32_t &qor, int (&sA)[kLB], bool &ovf)
+{
+    const int first = blk * kLB + 1;
+    const int last = kFull ? first + kLB - 1 : min(first + kLB - 1, n);
+    ovf |= S < ((first - 1 - kStartWinMax) << 7);
+    int Pt[kLB];
+    lane_prefix<kFull>(L, lane, first, n, q, P, qor, Pt);
+    uint32_t sat = 0;
+    int last_S = S;
+    const uint32_t lane4 = (uint32_t)lane << 2;
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
         if (!kFull && first + t > n) continue;
-        const int prev8 = (t == 0) ? s8 : sA[t - 1];
+        const int prev = (t == 0) ? S : sA[t - 1];
         const uint32_t T = (uint32_t)(Pt[t] - Q);
-        const int base8 = prev8 & ~15;
-        const int pr = (prev8 >> 4) & (kRingPairs - 1);
-        const uint32_t d0 = L.pp[pr][lane], d1 = L.pp[pr + 1][lane];
-        const uint32_t d2 = L.pp[pr + 2][lane], d3 = L.pp[pr + 3][lane];
-        const uint32_t m01 = __builtin_amdgcn_perm(pk_sub16(d1, T), pk_sub16(d0, T), 0x0b0a0908u);
-        const uint32_t m23 = __builtin_amdgcn_perm(pk_sub16(d3, T), pk_sub16(d2, T), 0x0b0a0908u);
-        sA[t] = __builtin_popcount(m23) + (__builtin_popcount(m01) + base8);
+        const uint32_t off = pp_row_off(prev, lane4);
+        const uint32_t d0 = lds_pp_at(L, off, 0), d1 = lds_pp_at(L, off, 1);
+        const uint32_t d2 = lds_pp_at(L, off, 2), d3 = lds_pp_at(L, off, 3);
+        const uint32_t m01 = sign_bytes(pk_sub16(d1, T), pk_sub16(d0, T));
+        const uint32_t m23 = sign_bytes(pk_sub16(d3, T), pk_sub16(d2, T));
+        sA[t] = start_from(prev, __builtin_popcount(m23) + __builtin_popcount(m01));
         sat |= m23;
-        last_base8 = base8;
+        last_S = prev;
     }
-    // Redo the block one position at a time if a lookahead saturated, or if one reached past
-    // the last written prefix (bases only grow, so the last one decides).
-    const bool rare = (int32_t)sat < 0 || last_base8 > 8 * (last - 7);
-    if (rare && !ovf) {
-        int s = s8 >> 3;
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-            if (!kFull && first + t > n) continue;
-            const uint32_t T = (uint32_t)(Pt[t] - Q);
-            while (pp_expired(L, lane, s, T)) ++s;
-            sA[t] = 8 * s;
-        }
-    }
-    s8 = sA[kFull ? kLB - 1 : (last - first)];
+    const bool rare = (int32_t)sat < 0 || (s_of(last_S) & ~1) > last - 7;
+    if (rare && !ovf) lane_starts_exact(L, lane, first, last, Q, S, Pt, sA);
+    S = sA[last - first];
 }
 
 __device__ __forceinline__ void lane_phase_a(LaneLds &L, int lane, int blk, int n, int Q,
-                                             const uint32_t (&q)[kLB], int &P, int &s8,
+                                             const uint32_t (&q)[kLB], int &P, int &S,
                                              uint32_t &qor, int (&sA)[kLB], bool &ovf)
 {
     if ((blk + 1) * kLB <= n)
-        lane_phase_a_impl<true>(L, lane, blk, n, Q, q, P, s8, qor, sA, ovf);
+        lane_phase_a_impl<true>(L, lane, blk, n, Q, q, P, S, qor, sA, ovf);
     else
-        lane_phase_a_impl<false>(L, lane, blk, n, Q, q, P, s8, qor, sA, ovf);
+        lane_phase_a_impl<false>(L, lane, blk, n, Q, q, P, S, qor, sA, ovf);
+}
+
+// Window starts of two consecutive states from one read of 12 positions starting at the
+// even position below the previous state's start: state t0 counts 8 of them, t1 all 12.
+__device__ __forceinline__ void lane_pair_starts(LaneLds &L, uint32_t lane4, int S_prev,
+                                                 uint32_t T0, uint32_t T1, int &o0, int &o1,
+                                                 uint32_t &sat)
+{
+    const uint32_t off = pp_row_off(S_prev, lane4);
+    const uint32_t d0 = lds_pp_at(L, off, 0), d1 = lds_pp_at(L, off, 1), d2 = lds_pp_at(L, off, 2);
+    const uint32_t d3 = lds_pp_at(L, off, 3), d4 = lds_pp_at(L, off, 4), d5 = lds_pp_at(L, off, 5);
+    const uint32_t a01 = sign_bytes(pk_sub16(d1, T0), pk_sub16(d0, T0));
+    const uint32_t a23 = sign_bytes(pk_sub16(d3, T0), pk_sub16(d2, T0));
+    o0 = start_from(S_prev, __builtin_popcount(a23) + __builtin_popcount(a01));
+    const uint32_t b01 = sign_bytes(pk_sub16(d1, T1), pk_sub16(d0, T1));
+    const uint32_t b23 = sign_bytes(pk_sub16(d3, T1), pk_sub16(d2, T1));
+    const uint32_t b45 = sign_bytes(pk_sub16(d5, T1), pk_sub16(d4, T1));
+    o1 = start_from(S_prev, __builtin_popcount(b45) + (__builtin_popcount(b23) +
+                                                        __builtin_popcount(b01)));
+    sat |= a23 | b45;  // sign bit: t0's 8th or t1's 12th position expired too
+}
+
+// Minimum of g over [s, start of block c) plus the running minimum of block c.
+__device__ __forceinline__ int lane_query(LaneLds &L, int S, uint32_t lane8, int pre)
+{
+    int bm, bs;
+    lds_rec_at(L, S, lane8, bm, bs);
+    return min(min(bm + (int)lds_dl_at(L, S), bs), pre);
 }
 
 // DP of the positions p = 16*blk .. 16*blk + 15 (< n): g_p from the previous state's window
-// minimum m, then the window minimum of state p + 1 into m.
+// minimum m, then the window minimum of state p + 1 into m. This careful form also handles
+// windows inside the block, the empty window (q > Q) and the partial last block.
 __device__ __forceinline__ void lane_phase_b(LaneLds &L, int lane, int blk, int n,
                                              const int32_t *__restrict__ w, const int (&sA)[kLB],
                                              int &m, int &pre, int (&gb)[kLB], bool &err)
 {
     const int p0 = blk * kLB;
-    const bool full = p0 + kLB <= n;
-    const bool careful = !full || sA[kLB - 1] >= 8 * p0;
-    if (!__any(careful)) {
-        int v1[kLB], v2[kLB];
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-            v1[t] = L.sf[(sA[t] >> 3) & (4 * kLB - 1)][lane];
-            v2[t] = L.bs[(sA[t] >> 7) & 3][lane];
-        }
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-            const int g = m + w[p0 + t];
-            gb[t] = g;
-            pre = (t == 0) ? g : min(pre, g);
-            m = min(min(v1[t], v2[t]), pre);
-        }
-        return;
-    }
+    const uint32_t lane8 = (uint32_t)lane << 3;
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
         const int p = p0 + t;
@@ -237,7 +308,7 @@ __device__ __forceinline__ void lane_phase_b(LaneLds &L, int lane, int blk, int 
         const int g = (p == 0) ? w[0] : m + w[p];
         gb[t] = g;
         pre = (t == 0) ? g : min(pre, g);
-        const int s = sA[t] >> 3;
+        const int s = s_of(sA[t]);
         if (s >= p0) {
             err |= (s == p + 1);
             int mm = kInf;
@@ -246,25 +317,76 @@ __device__ __forceinline__ void lane_phase_b(LaneLds &L, int lane, int blk, int 
                 if (p0 + j >= s) mm = min(mm, gb[j]);
             m = mm;
         } else {
-            m = min(min(L.sf[s & (4 * kLB - 1)][lane], L.bs[(s >> 4) & 3][lane]), pre);
+            m = lane_query(L, sA[t], lane8, pre);
         }
     }
 }
 
-// Suffix minima of block blk into sf, and the between-block minima into bs.
-__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, int blk, const int (&gb)[kLB])
+// Block blk complete: suffix minima as 16-bit offsets from the block minimum, the block's
+// record, and the between-block minima of the older blocks. A scenario whose offsets do not
+// fit 16 bits goes to the general kernel.
+__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, int blk, const int (&gb)[kLB],
+                                               bool &ovf)
 {
     const int p0 = blk * kLB;
-    int sm = gb[kLB - 1];
-    L.sf[(p0 + kLB - 1) & (4 * kLB - 1)][lane] = sm;
+    int sm[kLB];
+    sm[kLB - 1] = gb[kLB - 1];
 #pragma unroll
-    for (int t = kLB - 2; t >= 0; --t) {
-        sm = min(sm, gb[t]);
-        L.sf[(p0 + t) & (4 * kLB - 1)][lane] = sm;
+    for (int t = kLB - 2; t >= 0; --t) sm[t] = min(sm[t + 1], gb[t]);
+    const int bm = sm[0];
+    ovf |= (unsigned)(sm[kLB - 1] - bm) > 0xFFFFu;  // the largest offset is the last one
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) L.dl[(p0 + t) & (4 * kLB - 1)][lane] = (uint16_t)(sm[t] - bm);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L.rec[j][lane][1] = min(L.rec[j][lane][1], bm);
+    L.rec[blk & 3][lane][0] = bm;
+    L.rec[blk & 3][lane][1] = kInf;
+}
+
+// The common step, in one straight-line block so that the chain of LDS reads behind the
+// window starts of block blk + 1 overlaps the DP arithmetic of block blk. Requires blocks
+// blk and blk + 1 complete and every window of block blk to start in an older block.
+__device__ __forceinline__ void lane_fast_step(LaneLds &L, int lane, int blk, int Q,
+                                               const int32_t *__restrict__ w,
+                                               const uint32_t (&qUse)[kLB], const int (&sCur)[kLB],
+                                               int (&sNext)[kLB], int &P, int &S, uint32_t &qor,
+                                               int &m, int &pre, bool &ovf)
+{
+    const int p0 = blk * kLB;
+    const int first = p0 + kLB + 1;  // states of block blk + 1
+    const uint32_t lane4 = (uint32_t)lane << 2, lane8 = (uint32_t)lane << 3;
+    ovf |= S < ((first - 1 - kStartWinMax) << 7);
+    int Pt[kLB];
+    lane_prefix<true>(L, lane, first, first + kLB, qUse, P, qor, Pt);
+    int v1[kLB], v2[kLB];
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+        int bm, bs;
+        lds_rec_at(L, sCur[t], lane8, bm, bs);
+        v1[t] = bm + (int)lds_dl_at(L, sCur[t]);
+        v2[t] = bs;
     }
+    uint32_t sat = 0;
+    int gb[kLB];
+    const int S_start = S;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) L.bs[j][lane] = min(L.bs[j][lane], sm);
-    L.bs[blk & 3][lane] = kInf;
+    for (int u = 0; u < kLB / 2; ++u) {
+        const int prev = (u == 0) ? S_start : sNext[2 * u - 1];
+        lane_pair_starts(L, lane4, prev, (uint32_t)(Pt[2 * u] - Q), (uint32_t)(Pt[2 * u + 1] - Q),
+                         sNext[2 * u], sNext[2 * u + 1], sat);
+#pragma unroll
+        for (int t = 2 * u; t < 2 * u + 2; ++t) {
+            const int g = m + w[p0 + t];
+            gb[t] = g;
+            pre = (t == 0) ? g : min(pre, g);
+            m = min(min(v1[t], v2[t]), pre);
+        }
+    }
+    lane_block_end(L, lane, blk, gb, ovf);
+    const int last = first + kLB - 1;
+    const bool rare = (int32_t)sat < 0 || (s_of(sNext[kLB - 2]) & ~1) > last - 11;
+    if (rare && !ovf) lane_starts_exact(L, lane, first, last, Q, S_start, Pt, sNext);
+    S = sNext[kLB - 1];
 }
 
 // Demands of the states of block blk, by buffer loads: the descriptor holds the demand base,
@@ -280,34 +402,40 @@ __device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
         q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t + 1], 0);
 }
 
-// One block step: window starts of block blk + 1, DP of block blk, demands of block blk + 2.
+// One block step: demands of block blk + 2, window starts of block blk + 1, DP of block blk.
 __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int blk, int nblk, int n, int Q,
                                           __amdgpu_buffer_rsrc_t dem,
                                           const int64_t *__restrict__ rowoff, uint32_t lane_off,
                                           const int32_t *__restrict__ w, uint32_t (&qUse)[kLB],
                                           uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
-                                          int (&sNext)[kLB], int &P, int &s8, uint32_t &qor,
+                                          int (&sNext)[kLB], int &P, int &S, uint32_t &qor,
                                           int &m, int &pre, bool &err, bool &ovf)
 {
     // unconditional (rows past n are padding): keeps the load queue's wait counts exact
     lane_load_block(dem, rowoff, lane_off, blk + 2, qLoad);
-    if (blk + 1 < nblk) lane_phase_a(L, lane, blk + 1, n, Q, qUse, P, s8, qor, sNext, ovf);
+    const int p0 = blk * kLB;
+    const bool fast = (blk + 2) * kLB <= n && !__any(sCur[kLB - 1] >= (p0 << 7));
+    if (fast) {
+        lane_fast_step(L, lane, blk, Q, w, qUse, sCur, sNext, P, S, qor, m, pre, ovf);
+        return;
+    }
+    if (blk + 1 < nblk) lane_phase_a(L, lane, blk + 1, n, Q, qUse, P, S, qor, sNext, ovf);
     int gb[kLB];
     lane_phase_b(L, lane, blk, n, w, sCur, m, pre, gb, err);
-    if (blk + 1 < nblk) lane_block_end(L, lane, blk, gb);
+    if (blk + 1 < nblk) lane_block_end(L, lane, blk, gb, ovf);
 }
 
 // rowoff[i] here is the BYTE offset of position i's demand row.
 __global__ __launch_bounds__(64) void split_lane_kernel(
     const char *__restrict__ dem_ptr, const int64_t *__restrict__ rowoff,
     const int32_t *__restrict__ w, int32_t *__restrict__ cost, DevStats *__restrict__ stats,
-    int32_t *__restrict__ ovf_list, long long S, int n, int Q)
+    int32_t *__restrict__ ovf_list, long long nscen, int n, int Q)
 {
     __shared__ LaneLds L;
     const int lane = threadIdx.x;
     const long long scen_raw = (long long)blockIdx.x * 64 + lane;
-    const bool active = scen_raw < S;
-    const long long scen = active ? scen_raw : S - 1;
+    const bool active = scen_raw < nscen;
+    const long long scen = active ? scen_raw : nscen - 1;
     const uint32_t lane_off = (uint32_t)scen * 2u;
     // raw buffer over the whole demand matrix (gfx9 descriptor word 3: 0x00020000)
     const __amdgpu_buffer_rsrc_t rsrc =
@@ -315,9 +443,12 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
 
     pp_write(L, lane, 0, 0u);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) L.bs[j][lane] = kInf;
+    for (int j = 0; j < 4; ++j) {
+        L.rec[j][lane][0] = kInf;
+        L.rec[j][lane][1] = kInf;
+    }
 
-    int P = 0, s8 = 0, m = 0, pre = kInf;
+    int P = 0, S = S_of(0, lane), m = 0, pre = kInf;
     bool err = false, ovf = false;
     // OR of the raw 16-bit demands: bit 15 marks a negative int16 demand, which the 16-bit
     // window test cannot see (it wraps); demands in (Q, 2^15) empty the window instead.
@@ -328,18 +459,18 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     int s0[kLB], s1[kLB];
     lane_load_block(rsrc, rowoff, lane_off, 0, q0);
     lane_load_block(rsrc, rowoff, lane_off, 1, q1);
-    lane_phase_a(L, lane, 0, n, Q, q0, P, s8, qor, s0, ovf);
+    lane_phase_a(L, lane, 0, n, Q, q0, P, S, qor, s0, ovf);
     // blocks alternate the roles of (q0, q1) and (s0, s1); the loop body has no conditional
     // step so the compiler's load-wait counts stay exact across iterations
     int blk = 0;
     for (; blk + 1 < nblk; blk += 2) {
-        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, s8, qor,
+        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, S, qor,
                   m, pre, err, ovf);
-        lane_step(L, lane, blk + 1, nblk, n, Q, rsrc, rowoff, lane_off, w, q0, q1, s1, s0, P, s8,
+        lane_step(L, lane, blk + 1, nblk, n, Q, rsrc, rowoff, lane_off, w, q0, q1, s1, s0, P, S,
                   qor, m, pre, err, ovf);
     }
     if (blk < nblk)
-        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, s8, qor,
+        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, S, qor,
                   m, pre, err, ovf);
 
     err |= (qor & 0x8000u) != 0;
