@@ -66,6 +66,22 @@ def cpu_baseline(w, d, threads: int, target_cpu_s: float = 20.0):
                       f"{threads} threads, {el:.2f} s wall"}
 
 
+def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
+    """A plain copy kernel of known size: reads nbytes and writes nbytes per launch. Profiling
+    it with the same hardware counters gives the scale between counter readings and bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(7)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "ms_per_copy": el * 1e3, "GBps_read_plus_write": 2 * nbytes / el / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +92,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=4096,
                     help="scenarios re-checked against the oracle after timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device-to-device copy of 2 GiB (HBM counter scale)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the scenario shards and the one 24-byte all-reduce of a multi-GPU run are "

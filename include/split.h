@@ -15,9 +15,10 @@
  *  - Every function returns split_status; nothing throws, aborts, or prints.
  *  - Node 0 is the depot; customers are 1..N. The return depot of the paper (n+1) is the
  *    depot's location, so the closing arc of a route ending at customer c is d[c][0].
- *  - Unlimited fleet, no route-length limit (the paper's "if applicable" limit is not used).
+ *  - Unlimited fleet, no route-length limit (the optional limit the paper mentions is not used).
  *  - A context is not thread-safe: use one context per host thread / stream.
- *  - Limits: 1 <= n <= N <= SPLIT_MAX_N, 1 <= Q <= 32767, 1 <= S < 2^31.
+ *  - Limits: 1 <= n <= N <= SPLIT_MAX_N, 1 <= Q <= 16383, 1 <= S < 2^31 (Q is bounded so that
+ *    a window's load difference, at most 2Q, fits a signed 16-bit compare).
  */
 #ifndef SPLIT_H
 #define SPLIT_H
