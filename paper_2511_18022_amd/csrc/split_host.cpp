@@ -40,6 +40,7 @@ struct split_ctx {
     // per-call device buffers
     int32_t *d_tour = nullptr;
     int64_t *d_rowoff = nullptr;
+    uint32_t *d_rowoff32 = nullptr;
     int32_t *d_w = nullptr;
     int32_t cap_n = 0;
     int32_t *d_ovf = nullptr;
@@ -129,14 +130,17 @@ split_status ensure_capacity(split_ctx *ctx, int32_t n, int64_t S)
         int32_t nn = n < 1024 ? 1024 : n;
         if (ctx->d_tour) (void)hipFree(ctx->d_tour);
         if (ctx->d_rowoff) (void)hipFree(ctx->d_rowoff);
+        if (ctx->d_rowoff32) (void)hipFree(ctx->d_rowoff32);
         if (ctx->d_w) (void)hipFree(ctx->d_w);
         ctx->d_tour = nullptr;
         ctx->d_rowoff = nullptr;
+        ctx->d_rowoff32 = nullptr;
         ctx->d_w = nullptr;
         ctx->cap_n = 0;
         if (hipMalloc(&ctx->d_tour, sizeof(int32_t) * nn) != hipSuccess ||
             hipMalloc(&ctx->d_rowoff, sizeof(int64_t) * (nn + 1 + kRowPad)) != hipSuccess ||
-            hipMalloc(&ctx->d_w, sizeof(int32_t) * (nn + 1)) != hipSuccess)
+            hipMalloc(&ctx->d_rowoff32, sizeof(uint32_t) * (nn + 1 + kRowPad)) != hipSuccess ||
+            hipMalloc(&ctx->d_w, sizeof(int32_t) * (nn + 1 + kRowPad)) != hipSuccess)
             return fail(ctx, SPLIT_E_NOMEM, "device allocation for n=%d failed", nn);
         for (int k = 0; k < kStages; ++k) {
             if (ctx->h_tour[k]) (void)hipHostFree(ctx->h_tour[k]);
@@ -250,6 +254,7 @@ void split_ctx_destroy(split_ctx *ctx)
         free_instance(ctx);
         if (ctx->d_tour) (void)hipFree(ctx->d_tour);
         if (ctx->d_rowoff) (void)hipFree(ctx->d_rowoff);
+        if (ctx->d_rowoff32) (void)hipFree(ctx->d_rowoff32);
         if (ctx->d_w) (void)hipFree(ctx->d_w);
         if (ctx->d_ovf) (void)hipFree(ctx->d_ovf);
         if (ctx->d_partials) (void)hipFree(ctx->d_partials);
@@ -380,6 +385,7 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
     pa.dist = ctx->d_dist;
     pa.ld = ld;
     pa.out.rowoff = ctx->d_rowoff;
+    pa.out.rowoff32 = ctx->d_rowoff32;
     pa.out.w = ctx->d_w;
     pa.stats = ctx->d_stats;
     HIP_TRY(ctx, launch_prep(pa, stream));
@@ -398,7 +404,9 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
     int form = ctx->form;
     if (form == SPLIT_FORM_AUTO) form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
     // The lane kernel addresses demands with 32-bit buffer offsets.
-    const bool lane_addressable = ((__int128)(max_id - 1) * ld + S) * 2 < ((__int128)1 << 32);
+    const __int128 lane_bytes = ((__int128)(max_id - 1) * ld + S) * 2;
+    const bool lane_addressable = lane_bytes <= (__int128)kRowAbsent;
+    ea.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
     if (form == SPLIT_FORM_LANE && !lane_addressable) form = SPLIT_FORM_WAVE;
     hipEvent_t stop = nullptr;
     st = timing_begin(ctx, stream, &stop);

@@ -26,13 +26,15 @@ struct DevStats {
 //   rowoff[i] = (s_i - 1) * ld * 2   (byte offset of position i's int16 demand row), 1 <= i <= n
 // With g_p = f_p + c(0, s_{p+1}) - D[p+1] (D[k] = tour arc sum up to position k), Eq. (3)
 // becomes g_i = w_i + min_{p in window(i)} g_p, and f_n = w_n + min_{p in window(n)} g_p.
-// rowoff entries past position n that the prep kernel fills with a valid row (kernels load
-// whole blocks of positions without per-position guards).
-constexpr int kRowPad = 64;
+// Both arrays carry kRowPad entries past position n (rowoff: a valid row; w: zero) so that the
+// kernels can read whole blocks of positions, up to six blocks past n, without guards.
+constexpr int kRowPad = 128;
 
 struct TourDev {
-    int64_t *rowoff;  // [n + 1 + kRowPad]
-    int32_t *w;       // [n + 1]
+    int64_t *rowoff;     // [n + 1 + kRowPad]
+    uint32_t *rowoff32;  // [n + 1 + kRowPad], rowoff mod 2^32 (exact when it is used);
+                         // kRowAbsent at position 0 and past n
+    int32_t *w;          // [n + 1 + kRowPad]
 };
 
 struct PrepArgs {
@@ -57,7 +59,12 @@ struct EvalArgs {
     int32_t *cost;           // device [S]
     DevStats *stats;
     int32_t *ovf_list;       // device [S]: scenarios handed to the general kernel
+    uint32_t lane_bytes;     // lane kernel: bytes of demand it may address, <= kRowAbsent
 };
+
+// rowoff32 value of a position without a demand (position 0, positions past n): beyond every
+// lane_bytes, so the lane kernel's range-checked buffer loads return 0 for it.
+constexpr uint32_t kRowAbsent = 0xFFFFFF00u;
 
 struct MomentArgs {
     const int32_t *cost;

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
     for (int k = tid + 1; k <= n; k += 1024) {
         const int sk = a.tour[k - 1];
         a.out.rowoff[k] = (long long)(sk - 1) * a.ld * (long long)sizeof(uint16_t);
+        a.out.rowoff32[k] = (uint32_t)a.out.rowoff[k];
         if (k < n) {
             const int sn = a.tour[k];
             const int link = arc_cost(a, sk, sn);
@@ -70,10 +71,16 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
         if (tid < off) red[tid] += red[tid + off];
         __syncthreads();
     }
-    // positions n+1 .. n+kRowPad read row 0 (valid memory): lets kernels load whole blocks
-    for (int k = n + 1 + tid; k <= n + kRowPad; k += 1024) a.out.rowoff[k] = 0;
+    // positions n+1 .. n+kRowPad: row 0 (valid memory) and weight 0, so that kernels can
+    // load whole blocks of positions past n without guards
+    for (int k = n + 1 + tid; k <= n + kRowPad; k += 1024) {
+        a.out.rowoff[k] = 0;
+        a.out.rowoff32[k] = kRowAbsent;
+        a.out.w[k] = 0;
+    }
     if (tid == 0) {
         a.out.rowoff[0] = 0;
+        a.out.rowoff32[0] = kRowAbsent;
         a.out.w[0] = arc_cost(a, 0, a.tour[0]);
         a.out.w[n] = (int32_t)(red[0] + arc_cost(a, a.tour[n - 1], 0));
         a.stats->sum = 0;
@@ -86,249 +93,194 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 
 // ------------------------------------------------------------------------- lane kernel
 //
-// One lane = one scenario; a workgroup is one wavefront of 64 scenarios. Positions are
-// processed in blocks of kLB = 16. Per lane, LDS holds (lane-interleaved, so a per-lane
-// index costs at most a two-way bank conflict):
-//   pp  : prefix loads P_p mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword k;
-//         the first kMirror dwords are repeated after the ring so a 6-dword read never wraps;
-//   dl  : for the last 4 blocks, the suffix minimum of g inside the block, stored as a 16-bit
-//         offset from the block's minimum;
-//   rec : per block b of the last 4, (minimum of g over b, minimum of the block minima
-//         strictly between b and the current block).
-// For state i with window [s, i-1] whose newest position i-1 lies in block c:
-//   s in an older block b:  min g = min(bm[b] + dl[s], between[b], running minimum of c),
-//   s in block c:           the window lies in block c, whose g values are in registers.
-// Window starts (Eq. (2)) come from the prefix loads: s_i = s_{i-1} + #{p >= s_{i-1} :
-// P_p < P_i - Q}. The count compares 8 (or 12) positions at once as packed 16-bit
-// differences; it is exact because every compared difference lies in [-Q - q_i, Q] with
-// Q < 2^14 and q_i < 2^15 (bit 15 of a demand is checked separately). Lanes whose last
-// looked-ahead position expired too, or whose lookahead reached past the written prefixes,
-// redo the block one position at a time. Scenarios whose windows outgrow the 64-position
-// history, or whose suffix-minimum offsets outgrow 16 bits, are queued for the general kernel.
-// A window start s is carried as S = (s << 7) | (lane << 1), which makes the dl offset, the
-// pp row and the even base below s one instruction each.
+// One lane = one scenario; a workgroup is one wavefront of 64 scenarios. States 0..n are
+// processed in blocks of kLB = 16 (block c = states 16c .. 16c+15). For state i, Eq. (3)'s
+// window is [s_i, i-1] with s_i = #{p : P_p < P_i - Q} (Eq. (2); P = prefix loads).
+//
+// LDS per wavefront, every array interleaved by lane:
+//   rec : per block slot c & 3, the pair (minimum of g over block c, minimum of the block
+//         minima strictly between block c and the block being evaluated);
+//   dl  : suffix minima of g inside each of the last 4 blocks, as 16-bit offsets from the
+//         block minimum (row = position & 63);
+//   pp  : prefix loads P mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword row
+//         k & 31; rows 0 .. kMirror-1 repeated after the ring so that a 4-row read never wraps.
+// The window minimum of a state of block c whose window starts at s in an older block b is
+//   min(rec[b].bm + dl[s], rec[b].bs, minimum of g over block c before the state).
+// Window starts advance by counting expired positions as packed 16-bit differences: the two
+// states of a pair share one read of 8 positions starting at the even position below the
+// previous start. A pair whose 8th position expired is completed one position at a time, and
+// so is a whole block when its reads reached past the written prefix loads. The counts are
+// exact while 8 * max(q) + Q < 2^15 (every compared difference then fits a signed 16-bit value).
+// Scenarios the kernel cannot finish exactly (that demand bound broken, a window longer than
+// its history, suffix offsets beyond 16 bits) are queued for the general kernel.
+//
+// A window start s is carried as S = (s << 7) | (lane << 1): the dl offset, the pp row, the
+// rec slot and the even base below s take one or two instructions each. The block loop is
+// unrolled four times so that every LDS store has a constant offset.
 
-constexpr int kLB = 16;            // positions per block
-constexpr int kRingPairs = 32;     // ring of 64 positions, two per dword
-constexpr int kMirror = 5;         // dwords mirrored after the ring
-constexpr int kStartWinMax = 46;   // longest window at a block start the lane kernel keeps
+constexpr int kLB = 16;         // states per block
+constexpr int kRingPairs = 32;  // prefix-load ring of 64 positions, two per dword
+constexpr int kMirror = 3;      // ring rows repeated after the ring
 
-struct LaneLds {
-    uint32_t pp[kRingPairs + kMirror][64];
+struct __attribute__((aligned(16))) LaneLds {
+    uint64_t rec[4][64];
     uint16_t dl[4 * kLB][64];
-    int32_t rec[4][64][2];
+    uint32_t pp[kRingPairs + kMirror][64];
 };
+constexpr uint32_t kRecOff = 0;
+constexpr uint32_t kDlOff = sizeof(uint64_t) * 4 * 64;
+constexpr uint32_t kPpOff = kDlOff + sizeof(uint16_t) * 4 * kLB * 64;
 
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
-typedef __attribute__((address_space(3))) volatile uint16_t lds_u16v;
-typedef __attribute__((address_space(3))) int32_t lds_i32;
 typedef __attribute__((address_space(3))) char lds_char;
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int s_of(int S) { return S >> 7; }
 __device__ __forceinline__ int S_of(int s, int lane) { return (s << 7) | (lane << 1); }
 
-__device__ __forceinline__ uint32_t lds_dl_at(LaneLds &L, int S)
+__device__ __forceinline__ const lds_char *lds_base(LaneLds &L)
 {
-    return *(lds_u16 *)((lds_char *)(&L.dl[0][0]) + (S & 0x1FFE));
-}
-// (block minimum, between-block minimum) of the block holding s
-__device__ __forceinline__ void lds_rec_at(LaneLds &L, int S, uint32_t lane8, int &bm, int &bs)
-{
-    const lds_i32 *r = (const lds_i32 *)((lds_char *)(&L.rec[0][0][0]) +
-                                         (((uint32_t)(S >> 2) & 0x600u) | lane8));
-    bm = r[0];
-    bs = r[1];
-}
-// byte offset of pp row (s >> 1) & 31 for this lane
-__device__ __forceinline__ uint32_t pp_row_off(int S, uint32_t lane4)
-{
-    return ((uint32_t)S & 0x1F00u) | lane4;
-}
-__device__ __forceinline__ uint32_t lds_pp_at(LaneLds &L, uint32_t off, int row)
-{
-    return *(lds_u32 *)((lds_char *)(&L.pp[0][0]) + off + row * 256);
+    return (const lds_char *)(&L);
 }
 
-// Packed 16-bit a - t in both halves (no borrow between the halves).
+// Window-minimum lookup of a start S (in an older block): the 16-bit suffix offset and the
+// block record; combined later by query_min so that the reads are in flight meanwhile.
+__device__ __forceinline__ void query_issue(LaneLds &L, int S, uint32_t lane8, uint32_t &dlv,
+                                            uint64_t &recv)
+{
+    dlv = *(const lds_u16 *)(lds_base(L) + kDlOff + ((uint32_t)S & 0x1FFEu));
+    recv = *(const lds_u64 *)(lds_base(L) + kRecOff + ((((uint32_t)S >> 2) & 0x600u) | lane8));
+}
+__device__ __forceinline__ int query_min(uint32_t dlv, uint64_t recv, int pre)
+{
+    const int bm = (int)(uint32_t)recv;
+    const int bs = (int)(uint32_t)(recv >> 32);
+    return min(min(bm + (int)dlv, bs), pre);
+}
+
+__device__ __forceinline__ uint32_t pp_at(LaneLds &L, uint32_t off, int row)
+{
+    return *(const lds_u32 *)(lds_base(L) + kPpOff + off + row * 256);
+}
+// 16-bit ring value of position p
+__device__ __forceinline__ uint32_t pp_pos(LaneLds &L, int lane, int p)
+{
+    const lds_u16 *h = (const lds_u16 *)(lds_base(L) + kPpOff);
+    return h[(((p >> 1) & (kRingPairs - 1)) * 64 + lane) * 2 + (p & 1)];
+}
+
+// Packed 16-bit a - t in both halves, t a 16-bit value (no borrow between the halves).
 __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t t)
 {
-    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
     const u16x2 av = __builtin_bit_cast(u16x2, a);
     const u16x2 tv = {(unsigned short)t, (unsigned short)t};
     return __builtin_bit_cast(uint32_t, av - tv);
 }
-
 // Bytes 0..3 = 0xFF where the matching 16-bit half of (lo.lo, lo.hi, hi.lo, hi.hi) is negative.
 __device__ __forceinline__ uint32_t sign_bytes(uint32_t hi, uint32_t lo)
 {
     return __builtin_amdgcn_perm(hi, lo, 0x0b0a0908u);
 }
 
-// Window start after counting expired positions from the even position below S_prev:
-// cnt8 = 8 * (number of expired positions among those read).
-__device__ __forceinline__ int start_from(int S_prev, uint32_t cnt8)
+// Exact start of a state with threshold T, advancing one position at a time from a start that
+// is not past it. Bounded: position i of the state is never expired, and the ring holds it.
+__device__ __forceinline__ int exact_start(LaneLds &L, int lane, int S, uint32_t T)
 {
-    return (int)(cnt8 << 4) + (S_prev & ~0x80);
-}
-
-// 16-bit stores, one per position: kept unmerged so no instruction packs two positions.
-__device__ __forceinline__ void pp_write(LaneLds &L, int lane, int pos, uint32_t P)
-{
-    lds_u16v *h = (lds_u16v *)(&L.pp[0][0]);
-    const int pr = (pos >> 1) & (kRingPairs - 1);
-    h[(pr * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
-    if (pr < kMirror) h[((pr + kRingPairs) * 64 + lane) * 2 + (pos & 1)] = (uint16_t)P;
-}
-
-__device__ __forceinline__ bool pp_expired(LaneLds &L, int lane, int pos, uint32_t T)
-{
-    const uint16_t *h = reinterpret_cast<const uint16_t *>(&L.pp[0][0]);
-    const int pr = (pos >> 1) & (kRingPairs - 1);
-    return (int16_t)(uint16_t)(h[(pr * 64 + lane) * 2 + (pos & 1)] - (uint16_t)T) < 0;
-}
-
-// Prefix loads of the states first .. first + 15 into the ring and Pt.
-template <bool kFull>
-__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, int first, int n,
-                                            const uint32_t (&q)[kLB], int &P, uint32_t &qor,
-                                            int (&Pt)[kLB])
-{
-#pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-        if (!kFull && first + t > n) continue;
-        P += q[t];
-        qor |= q[t];
-        Pt[t] = P;
-        pp_write(L, lane, first + t, (uint32_t)P);
+    int s = s_of(S);
+    for (int k = 0; k < 2 * kRingPairs; ++k) {
+        if ((int16_t)(uint16_t)(pp_pos(L, lane, s) - T) >= 0) break;
+        ++s;
     }
+    return S_of(s, lane);
 }
 
-// Exact one-position-at-a-time window starts for states first .. last (the rare path).
-__device__ __forceinline__ void lane_starts_exact(LaneLds &L, int lane, int first, int last,
-                                                  int Q, int S_start, const int (&Pt)[kLB],
-                                                  int (&sA)[kLB])
+// Prefix loads of block c (R = c & 3): q[j] is the demand of position 16c + j (zero where a
+// position does not exist). Writes the ring rows of the block and returns the packed
+// thresholds TT[k] = (P_{16c+2k} - Q, P_{16c+2k+1} - Q) mod 2^16.
+template <int R>
+__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint32_t (&q)[kLB],
+                                            uint32_t QQ, uint32_t &Plast, uint32_t &qor,
+                                            uint32_t (&TT)[kLB / 2])
 {
-    int s = s_of(S_start);
+    uint32_t prev = Plast;
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-        if (first + t > last) continue;
-        const uint32_t T = (uint32_t)(Pt[t] - Q);
-        while (pp_expired(L, lane, s, T)) ++s;
-        sA[t] = S_of(s, lane);
+    for (int k = 0; k < kLB / 2; ++k) {
+        const uint32_t q0 = q[2 * k], q1 = q[2 * k + 1];
+        const uint32_t E = ((q0 + q1) << 16) + q0;  // (q0, q0 + q1)
+        const u16x2 ev = __builtin_bit_cast(u16x2, E);
+        const u16x2 pv = __builtin_bit_cast(u16x2, prev);
+        const u16x2 bc = {pv.y, pv.y};
+        const uint32_t PP = __builtin_bit_cast(uint32_t, ev + bc);
+        prev = PP;
+        TT[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, PP) -
+                                                 __builtin_bit_cast(u16x2, QQ));
+        qor |= q0 | q1;
+        constexpr int row0 = 8 * R;
+        L.pp[(row0 + k) & (kRingPairs - 1)][lane] = PP;
+        if (((row0 + k) & (kRingPairs - 1)) < kMirror)
+            L.pp[((row0 + k) & (kRingPairs - 1)) + kRingPairs][lane] = PP;
     }
+    Plast = prev;
 }
 
-// Window starts of the states 16*blk + 1 .. 16*blk + 16 (those <= n), one state at a time
-// with an 8-position lookahead. Used for the first and the last block.
-// In: S = start of state 16*blk. Out: sA[t] = start of state 16*blk + t + 1; S = the last.
-template <bool kFull>
-__device__ __forceinline__ void lane_phase_a_impl(LaneLds &L, int lane, int blk, int n, int Q,
-                                                  const uint32_t (&q)[kLB], int &P, int &S,
-                                                  uint32_t &qor, int (&sA)[kLB], bool &ovf)
+__device__ __forceinline__ uint32_t tt_half(const uint32_t (&TT)[kLB / 2], int t)
 {
-    const int first = blk * kLB + 1;
-    const int last = kFull ? first + kLB - 1 : min(first + kLB - 1, n);
-    ovf |= S < ((first - 1 - kStartWinMax) << 7);
-    int Pt[kLB];
-    lane_prefix<kFull>(L, lane, first, n, q, P, qor, Pt);
-    uint32_t sat = 0;
-    int last_S = S;
+    return (t & 1) ? (TT[t >> 1] >> 16) : (TT[t >> 1] & 0xFFFFu);
+}
+
+// Window starts of the states first .. first + 15, one state at a time with an 8-position
+// lookahead, completed exactly where the lookahead saturated or reached past the last written
+// prefix load (first + 15). States past n (demand 0) get valid starts too. In: Sp = start of
+// state first - 1.
+__device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int first,
+                                                    const uint32_t (&TT)[kLB / 2], int Sp,
+                                                    int (&sOut)[kLB])
+{
     const uint32_t lane4 = (uint32_t)lane << 2;
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
-        if (!kFull && first + t > n) continue;
-        const int prev = (t == 0) ? S : sA[t - 1];
-        const uint32_t T = (uint32_t)(Pt[t] - Q);
-        const uint32_t off = pp_row_off(prev, lane4);
-        const uint32_t d0 = lds_pp_at(L, off, 0), d1 = lds_pp_at(L, off, 1);
-        const uint32_t d2 = lds_pp_at(L, off, 2), d3 = lds_pp_at(L, off, 3);
-        const uint32_t m01 = sign_bytes(pk_sub16(d1, T), pk_sub16(d0, T));
-        const uint32_t m23 = sign_bytes(pk_sub16(d3, T), pk_sub16(d2, T));
-        sA[t] = start_from(prev, __builtin_popcount(m23) + __builtin_popcount(m01));
-        sat |= m23;
-        last_S = prev;
+        const uint32_t T = tt_half(TT, t);
+        const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
+        const uint32_t d0 = pp_at(L, off, 0), d1 = pp_at(L, off, 1);
+        const uint32_t d2 = pp_at(L, off, 2), d3 = pp_at(L, off, 3);
+        const uint32_t a01 = sign_bytes(pk_sub16(d1, T), pk_sub16(d0, T));
+        const uint32_t a23 = sign_bytes(pk_sub16(d3, T), pk_sub16(d2, T));
+        const int base = Sp & ~0x80;
+        int Sn = base + (int)((__builtin_popcount(a23) + __builtin_popcount(a01)) << 4);
+        const bool redo = (int32_t)a23 < 0 || s_of(base) + 7 > first + kLB - 1;
+        if (redo) Sn = exact_start(L, lane, Sp, T);
+        sOut[t] = Sn;
+        Sp = Sn;
     }
-    const bool rare = (int32_t)sat < 0 || (s_of(last_S) & ~1) > last - 7;
-    if (rare && !ovf) lane_starts_exact(L, lane, first, last, Q, S, Pt, sA);
-    S = sA[last - first];
 }
 
-__device__ __forceinline__ void lane_phase_a(LaneLds &L, int lane, int blk, int n, int Q,
-                                             const uint32_t (&q)[kLB], int &P, int &S,
-                                             uint32_t &qor, int (&sA)[kLB], bool &ovf)
+// Window starts of a pair of states from one read of 8 positions at the even position below
+// the previous start Sp. sat < 0: the 8th position expired for the second state.
+__device__ __forceinline__ void lane_pair(LaneLds &L, uint32_t lane4, int Sp, uint32_t TT,
+                                          int &S0, int &S1, uint32_t &sat)
 {
-    if ((blk + 1) * kLB <= n)
-        lane_phase_a_impl<true>(L, lane, blk, n, Q, q, P, S, qor, sA, ovf);
-    else
-        lane_phase_a_impl<false>(L, lane, blk, n, Q, q, P, S, qor, sA, ovf);
-}
-
-// Window starts of two consecutive states from one read of 12 positions starting at the
-// even position below the previous state's start: state t0 counts 8 of them, t1 all 12.
-__device__ __forceinline__ void lane_pair_starts(LaneLds &L, uint32_t lane4, int S_prev,
-                                                 uint32_t T0, uint32_t T1, int &o0, int &o1,
-                                                 uint32_t &sat)
-{
-    const uint32_t off = pp_row_off(S_prev, lane4);
-    const uint32_t d0 = lds_pp_at(L, off, 0), d1 = lds_pp_at(L, off, 1), d2 = lds_pp_at(L, off, 2);
-    const uint32_t d3 = lds_pp_at(L, off, 3), d4 = lds_pp_at(L, off, 4), d5 = lds_pp_at(L, off, 5);
+    const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
+    const uint32_t d0 = pp_at(L, off, 0), d1 = pp_at(L, off, 1);
+    const uint32_t d2 = pp_at(L, off, 2), d3 = pp_at(L, off, 3);
+    const uint32_t T0 = TT & 0xFFFFu, T1 = TT >> 16;
     const uint32_t a01 = sign_bytes(pk_sub16(d1, T0), pk_sub16(d0, T0));
     const uint32_t a23 = sign_bytes(pk_sub16(d3, T0), pk_sub16(d2, T0));
-    o0 = start_from(S_prev, __builtin_popcount(a23) + __builtin_popcount(a01));
     const uint32_t b01 = sign_bytes(pk_sub16(d1, T1), pk_sub16(d0, T1));
     const uint32_t b23 = sign_bytes(pk_sub16(d3, T1), pk_sub16(d2, T1));
-    const uint32_t b45 = sign_bytes(pk_sub16(d5, T1), pk_sub16(d4, T1));
-    o1 = start_from(S_prev, __builtin_popcount(b45) + (__builtin_popcount(b23) +
-                                                        __builtin_popcount(b01)));
-    sat |= a23 | b45;  // sign bit: t0's 8th or t1's 12th position expired too
+    const int base = Sp & ~0x80;
+    S0 = base + (int)((__builtin_popcount(a23) + __builtin_popcount(a01)) << 4);
+    S1 = base + (int)((__builtin_popcount(b23) + __builtin_popcount(b01)) << 4);
+    sat = b23;
 }
 
-// Minimum of g over [s, start of block c) plus the running minimum of block c.
-__device__ __forceinline__ int lane_query(LaneLds &L, int S, uint32_t lane8, int pre)
+// Block c complete (R = c & 3): suffix minima as 16-bit offsets from the block minimum, and
+// the records of blocks c, c-1, c-2 (bm1, bm2: minima of blocks c-1, c-2).
+template <int R>
+__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, const int (&gb)[kLB],
+                                               int &bm1, int &bm2, bool &ovf)
 {
-    int bm, bs;
-    lds_rec_at(L, S, lane8, bm, bs);
-    return min(min(bm + (int)lds_dl_at(L, S), bs), pre);
-}
-
-// DP of the positions p = 16*blk .. 16*blk + 15 (< n): g_p from the previous state's window
-// minimum m, then the window minimum of state p + 1 into m. This careful form also handles
-// windows inside the block, the empty window (q > Q) and the partial last block.
-__device__ __forceinline__ void lane_phase_b(LaneLds &L, int lane, int blk, int n,
-                                             const int32_t *__restrict__ w, const int (&sA)[kLB],
-                                             int &m, int &pre, int (&gb)[kLB], bool &err)
-{
-    const int p0 = blk * kLB;
-    const uint32_t lane8 = (uint32_t)lane << 3;
-#pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-        const int p = p0 + t;
-        if (p >= n) continue;
-        const int g = (p == 0) ? w[0] : m + w[p];
-        gb[t] = g;
-        pre = (t == 0) ? g : min(pre, g);
-        const int s = s_of(sA[t]);
-        if (s >= p0) {
-            err |= (s == p + 1);
-            int mm = kInf;
-#pragma unroll
-            for (int j = 0; j <= t; ++j)
-                if (p0 + j >= s) mm = min(mm, gb[j]);
-            m = mm;
-        } else {
-            m = lane_query(L, sA[t], lane8, pre);
-        }
-    }
-}
-
-// Block blk complete: suffix minima as 16-bit offsets from the block minimum, the block's
-// record, and the between-block minima of the older blocks. A scenario whose offsets do not
-// fit 16 bits goes to the general kernel.
-__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, int blk, const int (&gb)[kLB],
-                                               bool &ovf)
-{
-    const int p0 = blk * kLB;
     int sm[kLB];
     sm[kLB - 1] = gb[kLB - 1];
 #pragma unroll
@@ -336,100 +288,157 @@ __device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, int blk, co
     const int bm = sm[0];
     ovf |= (unsigned)(sm[kLB - 1] - bm) > 0xFFFFu;  // the largest offset is the last one
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) L.dl[(p0 + t) & (4 * kLB - 1)][lane] = (uint16_t)(sm[t] - bm);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) L.rec[j][lane][1] = min(L.rec[j][lane][1], bm);
-    L.rec[blk & 3][lane][0] = bm;
-    L.rec[blk & 3][lane][1] = kInf;
+    for (int t = 0; t < kLB; ++t) L.dl[kLB * R + t][lane] = (uint16_t)(sm[t] - bm);
+    auto pack = [](int lo, int hi) {
+        return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+    };
+    L.rec[R][lane] = pack(bm, kInf);
+    L.rec[(R + 3) & 3][lane] = pack(bm1, bm);
+    L.rec[(R + 2) & 3][lane] = pack(bm2, min(bm, bm1));
+    bm2 = bm1;
+    bm1 = bm;
 }
 
-// The common step, in one straight-line block so that the chain of LDS reads behind the
-// window starts of block blk + 1 overlaps the DP arithmetic of block blk. Requires blocks
-// blk and blk + 1 complete and every window of block blk to start in an older block.
-__device__ __forceinline__ void lane_fast_step(LaneLds &L, int lane, int blk, int Q,
-                                               const int32_t *__restrict__ w,
-                                               const uint32_t (&qUse)[kLB], const int (&sCur)[kLB],
-                                               int (&sNext)[kLB], int &P, int &S, uint32_t &qor,
-                                               int &m, int &pre, bool &ovf)
+// DP of block c, state by state, for any window position (inside the block, or empty).
+// States past n (demand 0, weight 0) are evaluated too and not used.
+__device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
+                                                const int32_t *__restrict__ w,
+                                                const int (&sCur)[kLB], int (&gb)[kLB], bool &err)
 {
-    const int p0 = blk * kLB;
-    const int first = p0 + kLB + 1;  // states of block blk + 1
-    const uint32_t lane4 = (uint32_t)lane << 2, lane8 = (uint32_t)lane << 3;
-    ovf |= S < ((first - 1 - kStartWinMax) << 7);
-    int Pt[kLB];
-    lane_prefix<true>(L, lane, first, first + kLB, qUse, P, qor, Pt);
-    int v1[kLB], v2[kLB];
+    const int p0 = c * kLB;
+    const uint32_t lane8 = (uint32_t)lane << 3;
+    int pre = kInf;
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
-        int bm, bs;
-        lds_rec_at(L, sCur[t], lane8, bm, bs);
-        v1[t] = bm + (int)lds_dl_at(L, sCur[t]);
-        v2[t] = bs;
-    }
-    uint32_t sat = 0;
-    int gb[kLB];
-    const int S_start = S;
+        const int i = p0 + t;
+        int g;
+        if (i == 0) {
+            g = w[0];
+        } else {
+            const int s = s_of(sCur[t]);
+            int m;
+            if (s >= p0) {  // window inside the block, or empty (s == i: q_i > Q)
+                err |= (s >= i);
+                int mm = kInf;
 #pragma unroll
-    for (int u = 0; u < kLB / 2; ++u) {
-        const int prev = (u == 0) ? S_start : sNext[2 * u - 1];
-        lane_pair_starts(L, lane4, prev, (uint32_t)(Pt[2 * u] - Q), (uint32_t)(Pt[2 * u + 1] - Q),
-                         sNext[2 * u], sNext[2 * u + 1], sat);
-#pragma unroll
-        for (int t = 2 * u; t < 2 * u + 2; ++t) {
-            const int g = m + w[p0 + t];
-            gb[t] = g;
-            pre = (t == 0) ? g : min(pre, g);
-            m = min(min(v1[t], v2[t]), pre);
+                for (int j = 0; j < t; ++j)
+                    if (p0 + j >= s) mm = min(mm, gb[j]);
+                m = mm;
+            } else {
+                uint32_t dlv;
+                uint64_t recv;
+                query_issue(L, sCur[t], lane8, dlv, recv);
+                m = query_min(dlv, recv, pre);
+            }
+            g = w[i] + m;
         }
+        gb[t] = g;
+        pre = min(pre, g);
     }
-    lane_block_end(L, lane, blk, gb, ovf);
-    const int last = first + kLB - 1;
-    const bool rare = (int32_t)sat < 0 || (s_of(sNext[kLB - 2]) & ~1) > last - 11;
-    if (rare && !ovf) lane_starts_exact(L, lane, first, last, Q, S_start, Pt, sNext);
-    S = sNext[kLB - 1];
 }
 
-// Demands of the states of block blk, by buffer loads: the descriptor holds the demand base,
-// the row's byte offset is the scalar offset and the lane's scenario offset the vector one,
-// so no vector instruction goes into addressing. Needs N * ld * 2 < 2^32 (host-checked).
+// Demands of block blk, by buffer loads: the descriptor holds the demand base, the row's byte
+// offset is the scalar offset and the lane's scenario offset the vector one. rowoff is padded
+// past n with a valid row, so blocks past n load unguarded (their values are not used).
 __device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
-                                                const int64_t *__restrict__ rowoff,
+                                                const uint32_t *__restrict__ rowoff,
                                                 uint32_t lane_off, int blk, uint32_t (&q)[kLB])
 {
-    // rowoff is padded past n with a valid row, so the last block loads unguarded too
 #pragma unroll
     for (int t = 0; t < kLB; ++t)
-        q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t + 1], 0);
+        q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t], 0);
 }
 
-// One block step: demands of block blk + 2, window starts of block blk + 1, DP of block blk.
-__device__ __forceinline__ void lane_step(LaneLds &L, int lane, int blk, int nblk, int n, int Q,
+struct LaneState {
+    uint32_t Plast;  // high half: prefix load of the last position written to the ring
+    uint32_t qor;    // OR of the demands read
+    int bm1, bm2;    // minima of the last two completed blocks
+    int gres;        // g_n
+    bool err, ovf;
+};
+
+// One block step (R = c & 3): demands of block c + 2, window starts of block c + 1, DP of
+// block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 2.
+template <int R>
+__device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, uint32_t QQ,
                                           __amdgpu_buffer_rsrc_t dem,
-                                          const int64_t *__restrict__ rowoff, uint32_t lane_off,
-                                          const int32_t *__restrict__ w, uint32_t (&qUse)[kLB],
+                                          const uint32_t *__restrict__ rowoff, uint32_t lane_off,
+                                          const int32_t *__restrict__ w, const uint32_t (&qUse)[kLB],
                                           uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
-                                          int (&sNext)[kLB], int &P, int &S, uint32_t &qor,
-                                          int &m, int &pre, bool &err, bool &ovf)
+                                          int (&sNext)[kLB], LaneState &st)
 {
-    // unconditional (rows past n are padding): keeps the load queue's wait counts exact
-    lane_load_block(dem, rowoff, lane_off, blk + 2, qLoad);
-    const int p0 = blk * kLB;
-    const bool fast = (blk + 2) * kLB <= n && !__any(sCur[kLB - 1] >= (p0 << 7));
+    lane_load_block(dem, rowoff, lane_off, c + 2, qLoad);  // unconditional: exact wait counts
+    const int nb = n >> 4;
+    if (c > nb) return;
+    const int p0 = c * kLB;
+    const int first = p0 + kLB;  // states of block c + 1
+    const uint32_t lane4 = (uint32_t)lane << 2, lane8 = (uint32_t)lane << 3;
+    // the ring and the block records must still hold every window start of block c + 1
+    // (state 16c + 15 exists whenever block c + 1 does)
+    if (c + 1 <= nb) st.ovf |= sCur[kLB - 1] < ((p0 - 2 * kLB) << 7);
+    int gb[kLB];
+    const bool fast = c >= 1 && first + kLB - 1 <= n && !__any(sCur[kLB - 1] >= (p0 << 7));
     if (fast) {
-        lane_fast_step(L, lane, blk, Q, w, qUse, sCur, sNext, P, S, qor, m, pre, ovf);
+        uint32_t qd[kLB];
+        uint64_t qr[kLB];
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) query_issue(L, sCur[t], lane8, qd[t], qr[t]);
+        uint32_t TT[kLB / 2];
+        lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
+        uint32_t satv = 0;  // bit 7 - u: this lane's pair u saturated
+        int pre = kInf;
+#pragma unroll
+        for (int u = 0; u < kLB / 2; ++u) {
+            const int Sp = (u == 0) ? sCur[kLB - 1] : sNext[2 * u - 1];
+            uint32_t sat;
+            lane_pair(L, lane4, Sp, TT[u], sNext[2 * u], sNext[2 * u + 1], sat);
+            satv = __builtin_amdgcn_alignbit(satv, sat, 31);  // (satv << 1) | sign(sat)
+#pragma unroll
+            for (int t = 2 * u; t < 2 * u + 2; ++t) {
+                const int g = w[p0 + t] + query_min(qd[t], qr[t], pre);
+                gb[t] = g;
+                pre = min(pre, g);
+            }
+        }
+        lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
+        // the last pair read positions up to its base + 7; the ring is written up to first + 15
+        if (__any((s_of(sNext[kLB - 3]) & ~1) > first + kLB - 8)) {
+            lane_starts_careful(L, lane, first, TT, sCur[kLB - 1], sNext);
+        } else if (__any(satv != 0)) {
+#pragma unroll
+            for (int u = 0; u < kLB / 2; ++u) {
+                if (__any(satv & (0x80u >> u))) {
+                    sNext[2 * u] = exact_start(L, lane, sNext[2 * u], TT[u] & 0xFFFFu);
+                    sNext[2 * u + 1] = exact_start(L, lane, sNext[2 * u + 1], TT[u] >> 16);
+                }
+            }
+        }
         return;
     }
-    if (blk + 1 < nblk) lane_phase_a(L, lane, blk + 1, n, Q, qUse, P, S, qor, sNext, ovf);
-    int gb[kLB];
-    lane_phase_b(L, lane, blk, n, w, sCur, m, pre, gb, err);
-    if (blk + 1 < nblk) lane_block_end(L, lane, blk, gb, ovf);
+    // careful step (positions past n load demand 0)
+    if (c + 1 <= nb) {
+        uint32_t TT[kLB / 2];
+        lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
+        lane_starts_careful(L, lane, first, TT, sCur[kLB - 1], sNext);
+    }
+    lane_dp_careful(L, lane, c, w, sCur, gb, st.err);
+    if (c + 1 <= nb) {
+        lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
+    } else {
+        // block c holds state n
+        int gn = gb[0];
+#pragma unroll
+        for (int t = 1; t < kLB; ++t)
+            if ((n & (kLB - 1)) == t) gn = gb[t];
+        st.gres = gn;
+    }
 }
 
-// rowoff[i] here is the BYTE offset of position i's demand row.
+// rowoff[i]: byte offset of position i's demand row (32 bits: the host checks N * ld * 2 < 2^32).
 __global__ __launch_bounds__(64) void split_lane_kernel(
-    const char *__restrict__ dem_ptr, const int64_t *__restrict__ rowoff,
+    const char *__restrict__ dem_ptr, const uint32_t *__restrict__ rowoff,
     const int32_t *__restrict__ w, int32_t *__restrict__ cost, DevStats *__restrict__ stats,
-    int32_t *__restrict__ ovf_list, long long nscen, int n, int Q)
+    int32_t *__restrict__ ovf_list, long long nscen, int n, int Q, uint32_t lane_bytes)
 {
     __shared__ LaneLds L;
     const int lane = threadIdx.x;
@@ -437,51 +446,57 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     const bool active = scen_raw < nscen;
     const long long scen = active ? scen_raw : nscen - 1;
     const uint32_t lane_off = (uint32_t)scen * 2u;
-    // raw buffer over the whole demand matrix (gfx9 descriptor word 3: 0x00020000)
+    // raw buffer over the demand bytes the tour can address (gfx9 descriptor word 3:
+    // 0x00020000); loads at offsets past lane_bytes (absent positions) return 0
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)dem_ptr, (short)0, -1, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)dem_ptr, (short)0, (int)lane_bytes, 0x00020000);
+    const uint32_t QQ = (uint32_t)Q | ((uint32_t)Q << 16);
 
-    pp_write(L, lane, 0, 0u);
+    LaneState st;
+    st.Plast = 0;
+    st.qor = 0;
+    st.bm1 = kInf;
+    st.bm2 = kInf;
+    st.gres = 0;
+    st.err = false;
+    st.ovf = false;
+
+    const int nb = n >> 4;
+    uint32_t qA[kLB], qB[kLB];
+    int sA[kLB], sB[kLB];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        L.rec[j][lane][0] = kInf;
-        L.rec[j][lane][1] = kInf;
+    for (int t = 0; t < kLB; ++t) {
+        sA[t] = S_of(0, lane);
+        sB[t] = S_of(0, lane);
+    }
+    lane_load_block(rsrc, rowoff, lane_off, 0, qA);
+    lane_load_block(rsrc, rowoff, lane_off, 1, qB);
+    {
+        // block 0: position 0 has no demand (P_0 = 0, its row offset is absent); start 0
+        uint32_t TT[kLB / 2];
+        lane_prefix<0>(L, lane, qA, QQ, st.Plast, st.qor, TT);
+        lane_starts_careful(L, lane, 0, TT, S_of(0, lane), sA);
+    }
+    // blocks rotate the roles of (qA, qB) and (sA, sB); four steps per iteration keep the
+    // ring rows of every step constant
+    for (int c = 0; c <= nb; c += 4) {
+        lane_step<0>(L, lane, c, n, QQ, rsrc, rowoff, lane_off, w, qB, qA, sA, sB, st);
+        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, rowoff, lane_off, w, qA, qB, sB, sA, st);
+        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, rowoff, lane_off, w, qB, qA, sA, sB, st);
+        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, rowoff, lane_off, w, qA, qB, sB, sA, st);
     }
 
-    int P = 0, S = S_of(0, lane), m = 0, pre = kInf;
-    bool err = false, ovf = false;
-    // OR of the raw 16-bit demands: bit 15 marks a negative int16 demand, which the 16-bit
-    // window test cannot see (it wraps); demands in (Q, 2^15) empty the window instead.
-    uint32_t qor = 0;
-
-    const int nblk = (n + kLB - 1) / kLB;
-    uint32_t q0[kLB], q1[kLB];
-    int s0[kLB], s1[kLB];
-    lane_load_block(rsrc, rowoff, lane_off, 0, q0);
-    lane_load_block(rsrc, rowoff, lane_off, 1, q1);
-    lane_phase_a(L, lane, 0, n, Q, q0, P, S, qor, s0, ovf);
-    // blocks alternate the roles of (q0, q1) and (s0, s1); the loop body has no conditional
-    // step so the compiler's load-wait counts stay exact across iterations
-    int blk = 0;
-    for (; blk + 1 < nblk; blk += 2) {
-        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, S, qor,
-                  m, pre, err, ovf);
-        lane_step(L, lane, blk + 1, nblk, n, Q, rsrc, rowoff, lane_off, w, q0, q1, s1, s0, P, S,
-                  qor, m, pre, err, ovf);
-    }
-    if (blk < nblk)
-        lane_step(L, lane, blk, nblk, n, Q, rsrc, rowoff, lane_off, w, q1, q0, s0, s1, P, S, qor,
-                  m, pre, err, ovf);
-
-    err |= (qor & 0x8000u) != 0;
+    // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
+    // int16 demand) also lands here, and the general kernel reports it
+    st.ovf |= 8u * st.qor + (uint32_t)Q > 32767u;
     if (active) {
-        if (ovf) {
+        if (st.ovf) {
             const int k = atomicAdd(&stats->ovf_count, 1);
             ovf_list[k] = (int32_t)scen;
-        } else if (err) {
+        } else if (st.err) {
             atomicOr(&stats->err_demand, 1);
         } else {
-            cost[scen] = m + w[n];
+            cost[scen] = st.gres;
         }
     }
 }
@@ -656,8 +671,8 @@ hipError_t launch_lane(const EvalArgs &a, hipStream_t stream)
 {
     const long long nb = (a.S + 63) / 64;
     hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)nb), dim3(64), 0, stream,
-                       reinterpret_cast<const char *>(a.demand), a.tour.rowoff, a.tour.w, a.cost,
-                       a.stats, a.ovf_list, (long long)a.S, a.n, a.Q);
+                       reinterpret_cast<const char *>(a.demand), a.tour.rowoff32, a.tour.w, a.cost,
+                       a.stats, a.ovf_list, (long long)a.S, a.n, a.Q, a.lane_bytes);
     return hipGetLastError();
 }
 

@@ -199,6 +199,24 @@ def test_maximum_capacity_and_run_twice_determinism(ctx):
     assert np.array_equal(c, c2)
 
 
+@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("Q,lo,hi", [(16383, 4000, 16383), (16383, 1, 16383), (4681, 2000, 4681),
+                                     (3000, 0, 400)])
+def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi):
+    # demands close to Q make windows of one or two customers; the prefix-load differences the
+    # lane kernel compares in 16 bits then grow past 2^15 for positions ahead of a state
+    rng = np.random.default_rng(Q + lo)
+    N = 260
+    xy = gen.coords(13, N)
+    d = oracle.dist_matrix(xy)
+    tour = gen.tour(13, N)
+    S = 3000
+    dem = rng.integers(lo, hi + 1, size=(N, S)).astype(np.int16)
+    # a quarter of the scenarios with small demands (long windows) in the same launch
+    dem[:, : S // 4] = rng.integers(0, 40, size=(N, S // 4)).astype(np.int16)
+    check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
+
+
 def test_async_calls_and_stats_get(ctx):
     w = gen.make_workload("poisson-n200", S=10000)
     d = oracle.dist_matrix(w.xy)
