@@ -275,6 +275,41 @@ __device__ __forceinline__ void lane_pair(LaneLds &L, uint32_t lane4, int Sp, ui
     sat = b23;
 }
 
+// Materializes v at this point of the instruction stream (keeps the compiler from sinking a
+// computation towards a later use).
+__device__ __forceinline__ void pin(int &v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin_uniform16(int (&v)[16])
+{
+    asm volatile(""
+                 : "+s"(v[0]), "+s"(v[1]), "+s"(v[2]), "+s"(v[3]), "+s"(v[4]), "+s"(v[5]),
+                   "+s"(v[6]), "+s"(v[7]), "+s"(v[8]), "+s"(v[9]), "+s"(v[10]), "+s"(v[11]),
+                   "+s"(v[12]), "+s"(v[13]), "+s"(v[14]), "+s"(v[15]));
+}
+
+// The 8 positions a pair reads (4 packed dwords) and the even position they start at.
+struct PairData {
+    uint32_t d0, d1, d2, d3;
+    int base;
+};
+__device__ __forceinline__ PairData pair_read(LaneLds &L, uint32_t lane4, int Sp)
+{
+    PairData p;
+    const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
+    p.d0 = pp_at(L, off, 0);
+    p.d1 = pp_at(L, off, 1);
+    p.d2 = pp_at(L, off, 2);
+    p.d3 = pp_at(L, off, 3);
+    p.base = Sp & ~0x80;
+    return p;
+}
+// Start of a state with threshold T from a pair's positions; x23 < 0: the 8th expired.
+__device__ __forceinline__ int pair_count(const PairData &p, uint32_t T, uint32_t &x23)
+{
+    const uint32_t x01 = sign_bytes(pk_sub16(p.d1, T), pk_sub16(p.d0, T));
+    x23 = sign_bytes(pk_sub16(p.d3, T), pk_sub16(p.d2, T));
+    return p.base + (int)((__builtin_popcount(x23) + __builtin_popcount(x01)) << 4);
+}
+
 // Block c complete (R = c & 3): suffix minima as 16-bit offsets from the block minimum, and
 // the records of blocks c, c-1, c-2 (bm1, bm2: minima of blocks c-1, c-2).
 template <int R>
@@ -379,26 +414,56 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
     int gb[kLB];
     const bool fast = c >= 1 && first + kLB - 1 <= n && !__any(sCur[kLB - 1] >= (p0 << 7));
     if (fast) {
-        uint32_t qd[kLB];
-        uint64_t qr[kLB];
+        // Software pipeline over the 8 pairs of block c + 1 and the 16 states of block c.
+        // Iteration u: window lookups for the DP of the next pair, DP of states 2u, 2u+1,
+        // first state of pair u-1, then second state of pair u (whose read was issued at the
+        // end of iteration u-1) and the read of pair u+1. The scheduling barriers keep the
+        // independent work between each read and its first use.
+        // the block's weights, loaded up front: a scalar load inside the pipeline would make
+        // its wait drain every outstanding LDS read as well
+        int wv[kLB];
 #pragma unroll
-        for (int t = 0; t < kLB; ++t) query_issue(L, sCur[t], lane8, qd[t], qr[t]);
+        for (int t = 0; t < kLB; ++t) wv[t] = w[p0 + t];
+        pin_uniform16(wv);
         uint32_t TT[kLB / 2];
         lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
+        uint32_t qd[kLB];
+        uint64_t qr[kLB];
+        query_issue(L, sCur[0], lane8, qd[0], qr[0]);
+        query_issue(L, sCur[1], lane8, qd[1], qr[1]);
+        PairData pcur = pair_read(L, lane4, sCur[kLB - 1]);
+        PairData pprev = pcur;
         uint32_t satv = 0;  // bit 7 - u: this lane's pair u saturated
         int pre = kInf;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kLB / 2; ++u) {
-            const int Sp = (u == 0) ? sCur[kLB - 1] : sNext[2 * u - 1];
-            uint32_t sat;
-            lane_pair(L, lane4, Sp, TT[u], sNext[2 * u], sNext[2 * u + 1], sat);
-            satv = __builtin_amdgcn_alignbit(satv, sat, 31);  // (satv << 1) | sign(sat)
+            if (u + 1 < kLB / 2) {
+                query_issue(L, sCur[2 * u + 2], lane8, qd[2 * u + 2], qr[2 * u + 2]);
+                query_issue(L, sCur[2 * u + 3], lane8, qd[2 * u + 3], qr[2 * u + 3]);
+            }
 #pragma unroll
             for (int t = 2 * u; t < 2 * u + 2; ++t) {
-                const int g = w[p0 + t] + query_min(qd[t], qr[t], pre);
+                const int g = wv[t] + query_min(qd[t], qr[t], pre);
                 gb[t] = g;
                 pre = min(pre, g);
             }
+            if (u > 0) {
+                uint32_t x;
+                sNext[2 * u - 2] = pair_count(pprev, TT[u - 1] & 0xFFFFu, x);
+                pin(sNext[2 * u - 2]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t sat;
+            sNext[2 * u + 1] = pair_count(pcur, TT[u] >> 16, sat);
+            satv = __builtin_amdgcn_alignbit(satv, sat, 31);  // (satv << 1) | sign(sat)
+            pprev = pcur;
+            if (u + 1 < kLB / 2) pcur = pair_read(L, lane4, sNext[2 * u + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        {
+            uint32_t x;
+            sNext[kLB - 2] = pair_count(pprev, TT[kLB / 2 - 1] & 0xFFFFu, x);
         }
         lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
         // the last pair read positions up to its base + 7; the ring is written up to first + 15
