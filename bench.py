@@ -85,8 +85,9 @@ def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    # the GPU's clocks need a few tens of milliseconds of work to settle
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="copula-n1000")
     ap.add_argument("--form", default="auto", choices=["auto", "lane", "wave"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

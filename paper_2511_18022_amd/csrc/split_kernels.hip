@@ -103,14 +103,15 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 //   dl  : suffix minima of g inside each of the last 4 blocks, as 16-bit offsets from the
 //         block minimum (row = position & 63);
 //   pp  : prefix loads P mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword row
-//         k & 31; rows 0 .. kMirror-1 repeated after the ring so that a 4-row read never wraps.
+//         k & 31; rows 0 .. kMirror-1 repeated after the ring so that a 6-row read never wraps.
 // The window minimum of a state of block c whose window starts at s in an older block b is
 //   min(rec[b].bm + dl[s], rec[b].bs, minimum of g over block c before the state).
 // Window starts advance by counting expired positions as packed 16-bit differences: the two
-// states of a pair share one read of 8 positions starting at the even position below the
-// previous start. A pair whose 8th position expired is completed one position at a time, and
-// so is a whole block when its reads reached past the written prefix loads. The counts are
-// exact while 8 * max(q) + Q < 2^15 (every compared difference then fits a signed 16-bit value).
+// states of a pair share one read of 12 positions starting at the even position below the
+// previous start; the first counts 8 of them, the second all 12. A block where some lane's last
+// counted position expired (the count may be short), or where a read reached past the written
+// prefix loads, has its starts redone one state at a time. The counts are exact while
+// 8 * max(q) + Q < 2^15 (every compared difference then fits a signed 16-bit value).
 // Scenarios the kernel cannot finish exactly (that demand bound broken, a window longer than
 // its history, suffix offsets beyond 16 bits) are queued for the general kernel.
 //
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 
 constexpr int kLB = 16;         // states per block
 constexpr int kRingPairs = 32;  // prefix-load ring of 64 positions, two per dword
-constexpr int kMirror = 3;      // ring rows repeated after the ring
+constexpr int kMirror = 5;      // ring rows repeated after the ring
 
 struct __attribute__((aligned(16))) LaneLds {
     uint64_t rec[4][64];
@@ -256,25 +257,6 @@ __device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int fi
     }
 }
 
-// Window starts of a pair of states from one read of 8 positions at the even position below
-// the previous start Sp. sat < 0: the 8th position expired for the second state.
-__device__ __forceinline__ void lane_pair(LaneLds &L, uint32_t lane4, int Sp, uint32_t TT,
-                                          int &S0, int &S1, uint32_t &sat)
-{
-    const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
-    const uint32_t d0 = pp_at(L, off, 0), d1 = pp_at(L, off, 1);
-    const uint32_t d2 = pp_at(L, off, 2), d3 = pp_at(L, off, 3);
-    const uint32_t T0 = TT & 0xFFFFu, T1 = TT >> 16;
-    const uint32_t a01 = sign_bytes(pk_sub16(d1, T0), pk_sub16(d0, T0));
-    const uint32_t a23 = sign_bytes(pk_sub16(d3, T0), pk_sub16(d2, T0));
-    const uint32_t b01 = sign_bytes(pk_sub16(d1, T1), pk_sub16(d0, T1));
-    const uint32_t b23 = sign_bytes(pk_sub16(d3, T1), pk_sub16(d2, T1));
-    const int base = Sp & ~0x80;
-    S0 = base + (int)((__builtin_popcount(a23) + __builtin_popcount(a01)) << 4);
-    S1 = base + (int)((__builtin_popcount(b23) + __builtin_popcount(b01)) << 4);
-    sat = b23;
-}
-
 // Materializes v at this point of the instruction stream (keeps the compiler from sinking a
 // computation towards a later use).
 __device__ __forceinline__ void pin(int &v) { asm volatile("" : "+v"(v)); }
@@ -286,28 +268,67 @@ __device__ __forceinline__ void pin_uniform16(int (&v)[16])
                    "+s"(v[12]), "+s"(v[13]), "+s"(v[14]), "+s"(v[15]));
 }
 
-// The 8 positions a pair reads (4 packed dwords) and the even position they start at.
+// The 12 positions a pair reads (6 packed dwords) and the even position they start at.
 struct PairData {
-    uint32_t d0, d1, d2, d3;
+    uint32_t d[6];
     int base;
 };
 __device__ __forceinline__ PairData pair_read(LaneLds &L, uint32_t lane4, int Sp)
 {
     PairData p;
     const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
-    p.d0 = pp_at(L, off, 0);
-    p.d1 = pp_at(L, off, 1);
-    p.d2 = pp_at(L, off, 2);
-    p.d3 = pp_at(L, off, 3);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) p.d[r] = pp_at(L, off, r);
     p.base = Sp & ~0x80;
     return p;
 }
-// Start of a state with threshold T from a pair's positions; x23 < 0: the 8th expired.
-__device__ __forceinline__ int pair_count(const PairData &p, uint32_t T, uint32_t &x23)
+// Start of a state with threshold T counted over the first 2 * D positions of a pair's read;
+// last < 0: the last counted position expired too (the count may be short).
+template <int D>
+__device__ __forceinline__ int pair_count(const PairData &p, uint32_t T, uint32_t &last)
 {
-    const uint32_t x01 = sign_bytes(pk_sub16(p.d1, T), pk_sub16(p.d0, T));
-    x23 = sign_bytes(pk_sub16(p.d3, T), pk_sub16(p.d2, T));
-    return p.base + (int)((__builtin_popcount(x23) + __builtin_popcount(x01)) << 4);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < D; r += 2) {
+        const uint32_t x = sign_bytes(pk_sub16(p.d[r + 1], T), pk_sub16(p.d[r], T));
+        cnt = __builtin_popcount(x) + cnt;
+        last = x;
+    }
+    return p.base + (int)(cnt << 4);
+}
+
+// Window starts of the states first .. first + 15 from Sp (start of state first - 1) with the
+// pair counts; where a count may be short or a read reached past the written prefix loads
+// (first + 15), the block is redone state by state.
+__device__ __forceinline__ void lane_starts_pairs(LaneLds &L, int lane, int first,
+                                                  const uint32_t (&TT)[kLB / 2], int Sp,
+                                                  int (&sOut)[kLB])
+{
+    const uint32_t lane4 = (uint32_t)lane << 2;
+    const int S_in = Sp;
+    uint32_t sat = 0;
+#pragma unroll
+    for (int u = 0; u < kLB / 2; ++u) {
+        const PairData p = pair_read(L, lane4, Sp);
+        uint32_t x0, x1;
+        sOut[2 * u] = pair_count<4>(p, TT[u] & 0xFFFFu, x0);
+        sOut[2 * u + 1] = pair_count<6>(p, TT[u] >> 16, x1);
+        sat |= x0 | x1;
+        Sp = sOut[2 * u + 1];
+    }
+    if (__any((int32_t)sat < 0 || (s_of(sOut[kLB - 3]) & ~1) > first + kLB - 12))
+        lane_starts_careful(L, lane, first, TT, S_in, sOut);
+}
+
+// g of state t of a block (t uniform), without per-state masks kept across the block loop.
+__device__ __forceinline__ int block_g_at(const int (&gb)[kLB], int t)
+{
+    asm volatile("" : "+s"(t));
+    int g = gb[0];
+#pragma unroll
+    for (int k = 1; k < kLB; ++k)
+        if (t == k) g = gb[k];
+    return g;
 }
 
 // Block c complete (R = c & 3): suffix minima as 16-bit offsets from the block minimum, and
@@ -392,8 +413,8 @@ struct LaneState {
     bool err, ovf;
 };
 
-// One block step (R = c & 3): demands of block c + 2, window starts of block c + 1, DP of
-// block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 2.
+// One block step (R = c & 3): demands of block c + 3, window starts of block c + 1, DP of
+// block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 3.
 template <int R>
 __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, uint32_t QQ,
                                           __amdgpu_buffer_rsrc_t dem,
@@ -402,7 +423,7 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
                                           uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
                                           int (&sNext)[kLB], LaneState &st)
 {
-    lane_load_block(dem, rowoff, lane_off, c + 2, qLoad);  // unconditional: exact wait counts
+    lane_load_block(dem, rowoff, lane_off, c + 3, qLoad);  // unconditional: exact wait counts
     const int nb = n >> 4;
     if (c > nb) return;
     const int p0 = c * kLB;
@@ -412,7 +433,8 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
     // (state 16c + 15 exists whenever block c + 1 does)
     if (c + 1 <= nb) st.ovf |= sCur[kLB - 1] < ((p0 - 2 * kLB) << 7);
     int gb[kLB];
-    const bool fast = c >= 1 && first + kLB - 1 <= n && !__any(sCur[kLB - 1] >= (p0 << 7));
+    // states past n (demand 0, weight 0) are evaluated like the others and not used
+    const bool fast = c >= 1 && !__any(sCur[kLB - 1] >= (p0 << 7));
     if (fast) {
         // Software pipeline over the 8 pairs of block c + 1 and the 16 states of block c.
         // Iteration u: window lookups for the DP of the next pair, DP of states 2u, 2u+1,
@@ -433,7 +455,7 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
         query_issue(L, sCur[1], lane8, qd[1], qr[1]);
         PairData pcur = pair_read(L, lane4, sCur[kLB - 1]);
         PairData pprev = pcur;
-        uint32_t satv = 0;  // bit 7 - u: this lane's pair u saturated
+        uint32_t sat = 0;  // sign bit: some count of this lane may be short
         int pre = kInf;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -450,52 +472,42 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
             }
             if (u > 0) {
                 uint32_t x;
-                sNext[2 * u - 2] = pair_count(pprev, TT[u - 1] & 0xFFFFu, x);
+                sNext[2 * u - 2] = pair_count<4>(pprev, TT[u - 1] & 0xFFFFu, x);
+                sat |= x;
                 pin(sNext[2 * u - 2]);
             }
             __builtin_amdgcn_sched_barrier(0);
-            uint32_t sat;
-            sNext[2 * u + 1] = pair_count(pcur, TT[u] >> 16, sat);
-            satv = __builtin_amdgcn_alignbit(satv, sat, 31);  // (satv << 1) | sign(sat)
+            uint32_t x1;
+            sNext[2 * u + 1] = pair_count<6>(pcur, TT[u] >> 16, x1);
+            sat |= x1;
             pprev = pcur;
             if (u + 1 < kLB / 2) pcur = pair_read(L, lane4, sNext[2 * u + 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
         {
             uint32_t x;
-            sNext[kLB - 2] = pair_count(pprev, TT[kLB / 2 - 1] & 0xFFFFu, x);
+            sNext[kLB - 2] = pair_count<4>(pprev, TT[kLB / 2 - 1] & 0xFFFFu, x);
+            sat |= x;
         }
         lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
-        // the last pair read positions up to its base + 7; the ring is written up to first + 15
-        if (__any((s_of(sNext[kLB - 3]) & ~1) > first + kLB - 8)) {
+        // the last pair read positions up to its base + 11; the ring is written up to
+        // first + 15. Either condition below is rare: redo the block's starts state by state.
+        if (__any((int32_t)sat < 0 || (s_of(sNext[kLB - 3]) & ~1) > first + kLB - 12))
             lane_starts_careful(L, lane, first, TT, sCur[kLB - 1], sNext);
-        } else if (__any(satv != 0)) {
-#pragma unroll
-            for (int u = 0; u < kLB / 2; ++u) {
-                if (__any(satv & (0x80u >> u))) {
-                    sNext[2 * u] = exact_start(L, lane, sNext[2 * u], TT[u] & 0xFFFFu);
-                    sNext[2 * u + 1] = exact_start(L, lane, sNext[2 * u + 1], TT[u] >> 16);
-                }
-            }
-        }
+        if (c == nb) st.gres = block_g_at(gb, n & (kLB - 1));
         return;
     }
     // careful step (positions past n load demand 0)
     if (c + 1 <= nb) {
         uint32_t TT[kLB / 2];
         lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
-        lane_starts_careful(L, lane, first, TT, sCur[kLB - 1], sNext);
+        lane_starts_pairs(L, lane, first, TT, sCur[kLB - 1], sNext);
     }
     lane_dp_careful(L, lane, c, w, sCur, gb, st.err);
     if (c + 1 <= nb) {
         lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
     } else {
-        // block c holds state n
-        int gn = gb[0];
-#pragma unroll
-        for (int t = 1; t < kLB; ++t)
-            if ((n & (kLB - 1)) == t) gn = gb[t];
-        st.gres = gn;
+        st.gres = block_g_at(gb, n & (kLB - 1));  // block c holds state n
     }
 }
 
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     st.ovf = false;
 
     const int nb = n >> 4;
-    uint32_t qA[kLB], qB[kLB];
+    uint32_t qA[kLB], qB[kLB], qC[kLB], qD[kLB];
     int sA[kLB], sB[kLB];
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
@@ -536,19 +548,20 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     }
     lane_load_block(rsrc, rowoff, lane_off, 0, qA);
     lane_load_block(rsrc, rowoff, lane_off, 1, qB);
+    lane_load_block(rsrc, rowoff, lane_off, 2, qC);
     {
         // block 0: position 0 has no demand (P_0 = 0, its row offset is absent); start 0
         uint32_t TT[kLB / 2];
         lane_prefix<0>(L, lane, qA, QQ, st.Plast, st.qor, TT);
-        lane_starts_careful(L, lane, 0, TT, S_of(0, lane), sA);
+        lane_starts_pairs(L, lane, 0, TT, S_of(0, lane), sA);
     }
-    // blocks rotate the roles of (qA, qB) and (sA, sB); four steps per iteration keep the
-    // ring rows of every step constant
+    // block b's demands live in q[A, B, C, D][b & 3] and the starts rotate between sA and sB;
+    // four steps per iteration keep these roles and the ring rows of every step constant
     for (int c = 0; c <= nb; c += 4) {
-        lane_step<0>(L, lane, c, n, QQ, rsrc, rowoff, lane_off, w, qB, qA, sA, sB, st);
-        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, rowoff, lane_off, w, qA, qB, sB, sA, st);
-        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, rowoff, lane_off, w, qB, qA, sA, sB, st);
-        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, rowoff, lane_off, w, qA, qB, sB, sA, st);
+        lane_step<0>(L, lane, c, n, QQ, rsrc, rowoff, lane_off, w, qB, qD, sA, sB, st);
+        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, rowoff, lane_off, w, qC, qA, sB, sA, st);
+        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, rowoff, lane_off, w, qD, qB, sA, sB, st);
+        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, rowoff, lane_off, w, qA, qC, sB, sA, st);
     }
 
     // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
