@@ -320,14 +320,18 @@ __device__ __forceinline__ void lane_starts_pairs(LaneLds &L, int lane, int firs
         lane_starts_careful(L, lane, first, TT, S_in, sOut);
 }
 
-// g of state t of a block (t uniform), without per-state masks kept across the block loop.
+// g of state t of a block (t uniform). Written as explicit selects: the compiler would
+// otherwise turn it into an indexed load from a scratch copy of the whole block.
 __device__ __forceinline__ int block_g_at(const int (&gb)[kLB], int t)
 {
-    asm volatile("" : "+s"(t));
+    t = __builtin_amdgcn_readfirstlane(t);
     int g = gb[0];
 #pragma unroll
-    for (int k = 1; k < kLB; ++k)
-        if (t == k) g = gb[k];
+    for (int k = 1; k < kLB; ++k) {
+        int m = __builtin_amdgcn_readfirstlane(-(int)(t == k));
+        asm volatile("" : "+s"(m));  // an opaque 0 / -1 mask
+        g = (gb[k] & m) | (g & ~m);
+    }
     return g;
 }
 
