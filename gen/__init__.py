@@ -149,6 +149,50 @@ RECIPES = {
 }
 
 
+# name -> (instance size N, tours T, tour length range, S, Q, seed, demand law)
+BATCH_RECIPES = {
+    "batch-256": dict(N=1000, T=256, n_lo=100, n_hi=1000, S=65536, Q=500, seed=4,
+                      law=("copula", 0.6, 20.0, 0.5)),
+}
+
+
+@dataclass
+class BatchWorkload:
+    name: str
+    N: int
+    S: int
+    Q: int
+    seed: int
+    xy: np.ndarray
+    tours: list  # T int32 arrays of distinct customer ids, uneven lengths
+    demand: np.ndarray  # int16 [N, S]
+
+
+def batch_lengths(seed: int, T: int, lo: int, hi: int) -> np.ndarray:
+    """T tour lengths uniform on {lo..hi}, drawn from Philox (stream 7 of the seed)."""
+    u = np.zeros(T, dtype=np.int32)
+    for t in range(T):
+        r = philox4x32_10([t, 0, 7, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        u[t] = lo + int(r[0]) % (hi - lo + 1)
+    return u
+
+
+def make_batch_workload(name: str, T: int | None = None, S: int | None = None,
+                        threads=None) -> BatchWorkload:
+    """Candidate tours of uneven length over one instance and one scenario matrix: tour t is
+    the first n_t customers of an independent random permutation (a subset tour)."""
+    r = BATCH_RECIPES[name]
+    N, Q, seed = r["N"], r["Q"], r["seed"]
+    T = r["T"] if T is None else int(T)
+    S = r["S"] if S is None else int(S)
+    xy = coords(seed, N)
+    lens = batch_lengths(seed, T, r["n_lo"], r["n_hi"])
+    tours = [tour(seed, N, int(lens[t]), variant=t + 1) for t in range(T)]
+    law = r["law"]
+    dem = demand_copula(seed, N, S, law[1], law[2], law[3], Q, threads=threads)
+    return BatchWorkload(name, N, S, Q, seed, xy, tours, dem)
+
+
 def make_workload(name: str, S: int | None = None, threads=None) -> Workload:
     """Build one of the named synthetic workloads (optionally with fewer scenarios)."""
     r = RECIPES[name]

@@ -119,6 +119,37 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
  */
 split_status split_stats_get(split_ctx *ctx, split_stats *stats);
 
+/*
+ * Evaluate T giant tours of uneven length against the same S demand scenarios in one launch
+ * sequence: for every tour t, exactly what split_eval computes for it (Section 3, Eqs. (1)-(3);
+ * the sample-average statistics of Section 2 and the appendix). The tours are the candidates a
+ * search produces; the scenario matrix is read by all of them.
+ *  tours     HOST int32, the T tours concatenated; tour t is tours[tour_ptr[t] .. tour_ptr[t+1]),
+ *            distinct customer ids in 1..N within each tour (tours may share customers).
+ *  tour_ptr  HOST int64 [T + 1], tour_ptr[0] = 0, every tour of length 1..N.
+ *  demand    DEVICE int16 [N][ld] as in split_eval.
+ *  cost      DEVICE int32 [T][ldc], ldc >= S: cost[t * ldc + s] receives f(n_t) of tour t in
+ *            scenario s. Undefined for a tour whose status is SPLIT_E_DEMAND.
+ *  stats     HOST [T] or NULL; tour_status HOST int32 [T] or NULL (per tour SPLIT_OK or
+ *            SPLIT_E_DEMAND). If either is non-NULL the call blocks until both are filled; if
+ *            both are NULL the call only enqueues work (split_batch_stats_get collects them).
+ * Work is ordered by decreasing tour length over persistent workgroups. The library copies
+ * the tours; enqueued work reads `demand` and writes `cost` until the stream reaches it.
+ * Errors: as split_eval (SPLIT_E_TOUR names the tour), SPLIT_E_INVAL also when
+ * T * ceil(S / 64) >= 2^31; SPLIT_E_DEMAND when some tour's status is SPLIT_E_DEMAND.
+ */
+split_status split_eval_batch(split_ctx *ctx, const int32_t *tours, const int64_t *tour_ptr,
+                              int32_t T, const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                              int32_t *cost, int64_t ldc, split_stats *stats,
+                              int32_t *tour_status, void *hip_stream);
+
+/*
+ * Wait for the latest evaluation on ctx (split_eval counts as a batch of one) and fill
+ * stats[0 .. T-1] and tour_status[0 .. T-1] (either may be NULL). Returns SPLIT_E_DEMAND if
+ * some tour's status is SPLIT_E_DEMAND, SPLIT_E_INVAL if no call was made yet.
+ */
+split_status split_batch_stats_get(split_ctx *ctx, split_stats *stats, int32_t *tour_status);
+
 /* Choose the kernel form for later split_eval calls (default SPLIT_FORM_AUTO). */
 split_status split_set_form(split_ctx *ctx, int form);
 

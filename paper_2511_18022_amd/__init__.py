@@ -24,8 +24,9 @@ STATUS_NAMES = {0: "SPLIT_OK", -1: "SPLIT_E_INVAL", -2: "SPLIT_E_TOUR", -3: "SPL
 # Every function declared in include/split.h.
 EXPORTED = [
     "split_ctx_create", "split_ctx_destroy", "split_last_error", "split_instance_set_coords",
-    "split_instance_set_dist", "split_eval", "split_stats_get", "split_set_form",
-    "split_timing_enable", "split_timing_get", "split_timing_reset",
+    "split_instance_set_dist", "split_eval", "split_stats_get", "split_eval_batch",
+    "split_batch_stats_get", "split_set_form", "split_timing_enable", "split_timing_get",
+    "split_timing_reset",
 ]
 
 
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.split_instance_set_dist.argtypes = [P, i32, P]
     lib.split_eval.argtypes = [P, P, i32, P, i64, i64, i32, P, P, P]
     lib.split_stats_get.argtypes = [P, ctypes.POINTER(SplitStatsC)]
+    lib.split_eval_batch.argtypes = [P, P, P, i32, P, i64, i64, i32, P, i64, P, P, P]
+    lib.split_batch_stats_get.argtypes = [P, P, P]
     lib.split_set_form.argtypes = [P, ctypes.c_int]
     lib.split_timing_enable.argtypes = [P, ctypes.c_int]
     lib.split_timing_get.argtypes = [P, ctypes.POINTER(ctypes.c_double),
@@ -180,12 +183,75 @@ class SplitContext:
             stream = torch.cuda.current_stream(demand.device)
         sh = ctypes.c_void_p(stream.cuda_stream)
         out = SplitStatsC()
+        self._last_T = 1
         st = self._lib.split_eval(self._h, t.ctypes.data_as(ctypes.c_void_p), len(t),
                                   ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q),
                                   ctypes.c_void_p(cost.data_ptr()),
                                   ctypes.byref(out) if sync else None, sh)
         self._check(st)
         return cost, (self._stats(out) if sync else None)
+
+    def eval_batch(self, tours, demand, Q: int, S: int | None = None, cost=None,
+                   sync: bool = True, stream=None):
+        """Split every tour of `tours` (a sequence of customer-id arrays of uneven length) under
+        every scenario of `demand` (torch.int16 CUDA tensor [N, ld]) in one launch sequence.
+
+        Returns (cost [T, S] int32 CUDA tensor, [SplitStats] * T, [status] * T) when sync, else
+        (cost, None, None) with the work enqueued. A tour with an infeasible demand raises
+        SplitError(SPLIT_E_DEMAND) when sync; batch_stats() then still gives every tour's result.
+        """
+        import torch
+        np = _np()
+        parts = [np.ascontiguousarray(t, dtype=np.int32).ravel() for t in tours]
+        T = len(parts)
+        if T < 1:
+            raise ValueError("need at least one tour")
+        ptr = np.zeros(T + 1, dtype=np.int64)
+        ptr[1:] = np.cumsum([p.size for p in parts])
+        flat = np.ascontiguousarray(np.concatenate(parts) if T else np.zeros(0, np.int32))
+        if not (isinstance(demand, torch.Tensor) and demand.is_cuda and
+                demand.dtype == torch.int16 and demand.dim() == 2 and
+                demand.stride(1) == 1):
+            raise ValueError("demand must be a CUDA int16 tensor [N, ld] with unit column stride")
+        ld = demand.stride(0)
+        S = demand.shape[1] if S is None else int(S)
+        if S > demand.shape[1]:
+            raise ValueError(f"S={S} exceeds the demand tensor's {demand.shape[1]} columns")
+        if flat.size and demand.shape[0] < int(flat.max()) <= self.N:
+            raise ValueError("the demand tensor has fewer rows than the largest tour customer id")
+        if cost is None:
+            cost = torch.empty((T, max(S, 1)), dtype=torch.int32, device=demand.device)
+        elif not (cost.is_cuda and cost.dtype == torch.int32 and cost.dim() == 2 and
+                  cost.shape[0] >= T and cost.shape[1] >= S and cost.stride(1) == 1):
+            raise ValueError("cost must be a CUDA int32 tensor [>= T, >= S] with unit column "
+                             "stride")
+        if stream is None:
+            stream = torch.cuda.current_stream(demand.device)
+        sh = ctypes.c_void_p(stream.cuda_stream)
+        outs = (SplitStatsC * T)()
+        status = np.zeros(T, dtype=np.int32)
+        st = self._lib.split_eval_batch(
+            self._h, flat.ctypes.data_as(ctypes.c_void_p), ptr.ctypes.data_as(ctypes.c_void_p),
+            T, ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q), ctypes.c_void_p(cost.data_ptr()),
+            cost.stride(0), ctypes.cast(outs, ctypes.c_void_p) if sync else None,
+            status.ctypes.data_as(ctypes.c_void_p) if sync else None, sh)
+        self._last_T = T
+        self._check(st)
+        if not sync:
+            return cost, None, None
+        return cost, [self._stats(o) for o in outs], [int(x) for x in status]
+
+    def batch_stats(self):
+        """Statistics and per-tour status of the latest evaluation (waits for it)."""
+        np = _np()
+        T = getattr(self, "_last_T", 1)
+        outs = (SplitStatsC * T)()
+        status = np.zeros(T, dtype=np.int32)
+        st = self._lib.split_batch_stats_get(self._h, ctypes.cast(outs, ctypes.c_void_p),
+                                             status.ctypes.data_as(ctypes.c_void_p))
+        if st not in (SPLIT_OK, SPLIT_E_DEMAND):
+            self._check(st)
+        return [self._stats(o) for o in outs], [int(x) for x in status]
 
     def stats(self) -> SplitStats:
         out = SplitStatsC()

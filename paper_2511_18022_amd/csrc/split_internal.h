@@ -1,5 +1,10 @@
 // Internal interface between the C-ABI host layer (split_host.cpp) and the HIP kernels
 // (split_kernels.hip). Not installed; callers use include/split.h.
+//
+// Every evaluation is a batch of T >= 1 giant tours over one instance and one demand matrix
+// (split_eval is the batch of one). Per-tour arrays are concatenated: tour t's positions are
+// tours[tptr[t] .. tptr[t+1]) and its derived arrays start at abase(t) = tptr[t] + t * (1 +
+// kRowPad), each holding n_t + 1 + kRowPad entries.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,68 +15,89 @@ namespace splitgpu {
 // "Infinity" for DP values. Host checks guarantee |DP value| + |weight| < 2^30.
 constexpr int32_t kInf = 0x3fffffff;
 
-// Device-side result block of one evaluation (zeroed by the prep kernel of each call).
+// Cost mark of a scenario the lane kernel leaves to the general kernel (costs are >= 0).
+constexpr int32_t kCostOvf = INT32_MIN;
+
+// Device-side result block of one tour (zeroed by the prep kernel of each call).
 struct DevStats {
     unsigned long long sum;    // sum of costs
     unsigned long long sq_lo;  // sum of squared costs, low 64 bits
     unsigned long long sq_hi;  // sum of squared costs, high 64 bits
     int32_t err_demand;        // nonzero: some scenario has q > Q (or q < 0) on the tour
-    int32_t ovf_count;         // scenarios queued for the general kernel
+    int32_t ovf_count;         // scenarios of this tour finished by the general kernel
 };
 
-// Per-tour arrays built on the device by the prep kernel from the tour and the instance.
+// Batch-wide counters (reset by the prep kernel of each call).
+struct BatchCtl {
+    uint32_t head;       // next work item of the lane kernel's queue
+    uint32_t ovf_total;  // scenarios marked kCostOvf, over all tours
+};
+
+// Per-tour arrays built on the device by the prep kernel from the tours and the instance.
 //   w[0]   = c(0, s_1)                                    (g_0 = f_0 + a_0)
 //   w[i]   = c(s_i, 0) + c(0, s_{i+1}) - c(s_i, s_{i+1})   1 <= i <= n-1
 //   w[n]   = D[n] + c(s_n, 0)                             (turns g back into f at i = n)
 //   rowoff[i] = (s_i - 1) * ld * 2   (byte offset of position i's int16 demand row), 1 <= i <= n
 // With g_p = f_p + c(0, s_{p+1}) - D[p+1] (D[k] = tour arc sum up to position k), Eq. (3)
 // becomes g_i = w_i + min_{p in window(i)} g_p, and f_n = w_n + min_{p in window(n)} g_p.
-// Both arrays carry kRowPad entries past position n (rowoff: a valid row; w: zero) so that the
-// kernels can read whole blocks of positions, up to six blocks past n, without guards.
+// Each array carries kRowPad entries past position n (rowoff: a valid row; rowoff32: absent;
+// w: zero) so that the kernels can read whole blocks of positions, up to six blocks past n,
+// without guards.
 constexpr int kRowPad = 128;
 
+// rowoff32 value of a position without a demand (position 0, positions past n): beyond every
+// lane_bytes, so the lane kernel's range-checked buffer loads return 0 for it.
+constexpr uint32_t kRowAbsent = 0xFFFFFF00u;
+
+__host__ __device__ inline int64_t tour_abase(const int64_t *tptr, int t)
+{
+    return tptr[t] + (int64_t)t * (1 + kRowPad);
+}
+
 struct TourDev {
-    int64_t *rowoff;     // [n + 1 + kRowPad]
-    uint32_t *rowoff32;  // [n + 1 + kRowPad], rowoff mod 2^32 (exact when it is used);
-                         // kRowAbsent at position 0 and past n
-    int32_t *w;          // [n + 1 + kRowPad]
+    const int32_t *tours;  // [tptr[T]] concatenated tours
+    const int64_t *tptr;   // [T + 1]
+    const int32_t *order;  // [T] tours by decreasing length (the lane kernel's work order)
+    int32_t T;
+    int64_t *rowoff;       // concatenated, see above
+    uint32_t *rowoff32;    // rowoff mod 2^32 (exact where it is used), kRowAbsent where absent
+    int32_t *w;
 };
 
 struct PrepArgs {
-    const int32_t *tour;  // device [n]
-    int32_t n;
+    TourDev tour;
     int32_t N;
-    int32_t kind;         // 0: coordinates, 1: distance matrix
-    const int32_t *xy;    // device [(N+1)*2]
-    const int32_t *dist;  // device [(N+1)^2]
+    int32_t kind;          // 0: coordinates, 1: distance matrix
+    const int32_t *xy;     // device [(N+1)*2]
+    const int32_t *dist;   // device [(N+1)^2]
     int64_t ld;
-    TourDev out;
-    DevStats *stats;
+    DevStats *stats;       // [T]
+    BatchCtl *ctl;
 };
 
 struct EvalArgs {
     const uint16_t *demand;  // device, row-major [N][ld], read as unsigned (q > Q rejects q < 0)
     int64_t ld;
     int64_t S;
-    int32_t n;
     int32_t Q;
     TourDev tour;
-    int32_t *cost;           // device [S]
-    DevStats *stats;
-    int32_t *ovf_list;       // device [S]: scenarios handed to the general kernel
+    int32_t *cost;           // device [T][ldc]
+    int64_t ldc;
+    DevStats *stats;         // [T]
+    BatchCtl *ctl;
     uint32_t lane_bytes;     // lane kernel: bytes of demand it may address, <= kRowAbsent
+    int32_t lane_grid;       // lane kernel: persistent workgroups
+    int32_t maxn;            // longest tour of the batch (sizes the wave kernel's LDS)
 };
 
-// rowoff32 value of a position without a demand (position 0, positions past n): beyond every
-// lane_bytes, so the lane kernel's range-checked buffer loads return 0 for it.
-constexpr uint32_t kRowAbsent = 0xFFFFFF00u;
-
 struct MomentArgs {
-    const int32_t *cost;
+    const int32_t *cost;           // [T][ldc]
+    int64_t ldc;
     int64_t S;
-    unsigned long long *partials;  // [3 * nblocks]
-    int32_t nblocks;
-    DevStats *stats;
+    int32_t T;
+    unsigned long long *partials;  // [T][nblocks][3]
+    int32_t nblocks;               // per tour
+    DevStats *stats;               // [T]
 };
 
 // Kernel launchers (split_kernels.hip). All are asynchronous on `stream`.

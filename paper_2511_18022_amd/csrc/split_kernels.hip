@@ -46,23 +46,29 @@ __device__ __forceinline__ int32_t arc_cost(const PrepArgs &a, int u, int v)
     return a.dist[(long long)u * (a.N + 1) + v];
 }
 
-// ------------------------------------------------------------------------- prep
-
+// One workgroup per tour: the weights w, the row offsets and the padding of tour t, and the
+// zeroed result block of the tour. Workgroup 0 also resets the batch counters.
 __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 {
     __shared__ long long red[1024];
     const int tid = threadIdx.x;
-    const int n = a.n;
+    const int t = blockIdx.x;
+    const int32_t *tour = a.tour.tours + a.tour.tptr[t];
+    const int n = (int)(a.tour.tptr[t + 1] - a.tour.tptr[t]);
+    const int64_t ab = tour_abase(a.tour.tptr, t);
+    int64_t *rowoff = a.tour.rowoff + ab;
+    uint32_t *rowoff32 = a.tour.rowoff32 + ab;
+    int32_t *w = a.tour.w + ab;
     long long link_sum = 0;
     for (int k = tid + 1; k <= n; k += 1024) {
-        const int sk = a.tour[k - 1];
-        a.out.rowoff[k] = (long long)(sk - 1) * a.ld * (long long)sizeof(uint16_t);
-        a.out.rowoff32[k] = (uint32_t)a.out.rowoff[k];
+        const int sk = tour[k - 1];
+        rowoff[k] = (long long)(sk - 1) * a.ld * (long long)sizeof(uint16_t);
+        rowoff32[k] = (uint32_t)rowoff[k];
         if (k < n) {
-            const int sn = a.tour[k];
+            const int sn = tour[k];
             const int link = arc_cost(a, sk, sn);
             link_sum += link;
-            a.out.w[k] = arc_cost(a, sk, 0) + arc_cost(a, 0, sn) - link;
+            w[k] = arc_cost(a, sk, 0) + arc_cost(a, 0, sn) - link;
         }
     }
     red[tid] = link_sum;
@@ -71,23 +77,28 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
         if (tid < off) red[tid] += red[tid + off];
         __syncthreads();
     }
-    // positions n+1 .. n+kRowPad: row 0 (valid memory) and weight 0, so that kernels can
-    // load whole blocks of positions past n without guards
+    // positions n+1 .. n+kRowPad: row 0 (valid memory), absent for the lane kernel, weight 0,
+    // so that kernels can load whole blocks of positions past n without guards
     for (int k = n + 1 + tid; k <= n + kRowPad; k += 1024) {
-        a.out.rowoff[k] = 0;
-        a.out.rowoff32[k] = kRowAbsent;
-        a.out.w[k] = 0;
+        rowoff[k] = 0;
+        rowoff32[k] = kRowAbsent;
+        w[k] = 0;
     }
     if (tid == 0) {
-        a.out.rowoff[0] = 0;
-        a.out.rowoff32[0] = kRowAbsent;
-        a.out.w[0] = arc_cost(a, 0, a.tour[0]);
-        a.out.w[n] = (int32_t)(red[0] + arc_cost(a, a.tour[n - 1], 0));
-        a.stats->sum = 0;
-        a.stats->sq_lo = 0;
-        a.stats->sq_hi = 0;
-        a.stats->err_demand = 0;
-        a.stats->ovf_count = 0;
+        rowoff[0] = 0;
+        rowoff32[0] = kRowAbsent;
+        w[0] = arc_cost(a, 0, tour[0]);
+        w[n] = (int32_t)(red[0] + arc_cost(a, tour[n - 1], 0));
+        DevStats *st = a.stats + t;
+        st->sum = 0;
+        st->sq_lo = 0;
+        st->sq_hi = 0;
+        st->err_demand = 0;
+        st->ovf_count = 0;
+        if (t == 0) {
+            a.ctl->head = 0;
+            a.ctl->ovf_total = 0;
+        }
     }
 }
 
@@ -131,6 +142,12 @@ struct __attribute__((aligned(16))) LaneLds {
 constexpr uint32_t kRecOff = 0;
 constexpr uint32_t kDlOff = sizeof(uint64_t) * 4 * 64;
 constexpr uint32_t kPpOff = kDlOff + sizeof(uint16_t) * 4 * kLB * 64;
+
+// Read-only per-tour arrays (written by the prep kernel, a previous launch): the constant
+// address space lets every uniform read of them be a scalar load.
+typedef __attribute__((address_space(4))) const uint32_t cu32;
+typedef __attribute__((address_space(4))) const int32_t ci32;
+typedef __attribute__((address_space(4))) const int64_t ci64;
 
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
@@ -362,7 +379,7 @@ __device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, const int (
 // DP of block c, state by state, for any window position (inside the block, or empty).
 // States past n (demand 0, weight 0) are evaluated too and not used.
 __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
-                                                const int32_t *__restrict__ w,
+                                                ci32 *__restrict__ w,
                                                 const int (&sCur)[kLB], int (&gb)[kLB], bool &err)
 {
     const int p0 = c * kLB;
@@ -401,7 +418,7 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
 // offset is the scalar offset and the lane's scenario offset the vector one. rowoff is padded
 // past n with a valid row, so blocks past n load unguarded (their values are not used).
 __device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
-                                                const uint32_t *__restrict__ rowoff,
+                                                cu32 *__restrict__ rowoff,
                                                 uint32_t lane_off, int blk, uint32_t (&q)[kLB])
 {
 #pragma unroll
@@ -422,8 +439,8 @@ struct LaneState {
 template <int R>
 __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, uint32_t QQ,
                                           __amdgpu_buffer_rsrc_t dem,
-                                          const uint32_t *__restrict__ rowoff, uint32_t lane_off,
-                                          const int32_t *__restrict__ w, const uint32_t (&qUse)[kLB],
+                                          cu32 *__restrict__ rowoff, uint32_t lane_off,
+                                          ci32 *__restrict__ w, const uint32_t (&qUse)[kLB],
                                           uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
                                           int (&sNext)[kLB], LaneState &st)
 {
@@ -515,22 +532,24 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
     }
 }
 
-// rowoff[i]: byte offset of position i's demand row (32 bits: the host checks N * ld * 2 < 2^32).
-__global__ __launch_bounds__(64) void split_lane_kernel(
-    const char *__restrict__ dem_ptr, const uint32_t *__restrict__ rowoff,
-    const int32_t *__restrict__ w, int32_t *__restrict__ cost, DevStats *__restrict__ stats,
-    int32_t *__restrict__ ovf_list, long long nscen, int n, int Q, uint32_t lane_bytes)
+// One work item: the 64 scenarios sb*64 .. sb*64+63 of tour t.
+__device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, long long sb,
+                                          __amdgpu_buffer_rsrc_t rsrc)
 {
-    __shared__ LaneLds L;
     const int lane = threadIdx.x;
-    const long long scen_raw = (long long)blockIdx.x * 64 + lane;
+    const long long nscen = a.S;
+    // tour values come from memory: state that they are the same on every lane
+    ci64 *tptr = (ci64 *)a.tour.tptr;
+    const int64_t p0 = tptr[t];
+    const int n = (int)(tptr[t + 1] - p0);
+    const int64_t ab = p0 + (int64_t)t * (1 + kRowPad);
+    cu32 *__restrict__ rowoff = (cu32 *)a.tour.rowoff32 + ab;
+    ci32 *__restrict__ w = (ci32 *)a.tour.w + ab;
+    const long long scen_raw = sb * 64 + lane;
     const bool active = scen_raw < nscen;
     const long long scen = active ? scen_raw : nscen - 1;
     const uint32_t lane_off = (uint32_t)scen * 2u;
-    // raw buffer over the demand bytes the tour can address (gfx9 descriptor word 3:
-    // 0x00020000); loads at offsets past lane_bytes (absent positions) return 0
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)dem_ptr, (short)0, (int)lane_bytes, 0x00020000);
+    const int Q = a.Q;
     const uint32_t QQ = (uint32_t)Q | ((uint32_t)Q << 16);
 
     LaneState st;
@@ -546,9 +565,9 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     uint32_t qA[kLB], qB[kLB], qC[kLB], qD[kLB];
     int sA[kLB], sB[kLB];
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-        sA[t] = S_of(0, lane);
-        sB[t] = S_of(0, lane);
+    for (int k = 0; k < kLB; ++k) {
+        sA[k] = S_of(0, lane);
+        sB[k] = S_of(0, lane);
     }
     lane_load_block(rsrc, rowoff, lane_off, 0, qA);
     lane_load_block(rsrc, rowoff, lane_off, 1, qB);
@@ -571,15 +590,43 @@ __global__ __launch_bounds__(64) void split_lane_kernel(
     // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
     // int16 demand) also lands here, and the general kernel reports it
     st.ovf |= 8u * st.qor + (uint32_t)Q > 32767u;
+    int32_t *cost = a.cost + (long long)t * a.ldc;
     if (active) {
         if (st.ovf) {
-            const int k = atomicAdd(&stats->ovf_count, 1);
-            ovf_list[k] = (int32_t)scen;
+            cost[scen] = kCostOvf;
+            atomicAdd(&a.stats[t].ovf_count, 1);
+            atomicAdd(&a.ctl->ovf_total, 1u);
         } else if (st.err) {
-            atomicOr(&stats->err_demand, 1);
+            atomicOr(&a.stats[t].err_demand, 1);
         } else {
             cost[scen] = st.gres;
         }
+    }
+}
+
+// Persistent: each workgroup takes (tour, scenario block) items from a queue in the order of
+// decreasing tour length until the queue is empty. The next item's index is fetched while the
+// current one runs.
+__global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
+{
+    __shared__ LaneLds L;
+    const int lane = threadIdx.x;
+    // raw buffer over the demand bytes the tours can address (gfx9 descriptor word 3:
+    // 0x00020000); loads at offsets past lane_bytes (absent positions) return 0
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)a.demand, (short)0, (int)a.lane_bytes, 0x00020000);
+    const long long nsb = (a.S + 63) / 64;
+    const long long items = nsb * a.tour.T;
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(&a.ctl->head, 1u);
+    k = __builtin_amdgcn_readfirstlane(k);
+    while ((long long)k < items) {
+        uint32_t knext = 0;
+        if (lane == 0) knext = atomicAdd(&a.ctl->head, 1u);
+        const long long r = (long long)k / nsb;
+        const int t = ((ci32 *)a.tour.order)[r];
+        lane_item(L, a, t, (long long)k - r * nsb, rsrc);
+        k = __builtin_amdgcn_readfirstlane(knext);
     }
 }
 
@@ -615,25 +662,28 @@ __device__ __forceinline__ int wave_exclusive_sum(int v)
 // lanes loading demands in parallel (chunk per lane + wavefront scan). Then, state by state,
 // every lane runs the same two-pointer on the same data (uniform control flow), lane j reads
 // g of predecessor s + j (+ 64k for long windows) and the wavefront reduces them.
-__device__ void wave_one(const EvalArgs &a, long long scen, int32_t *G, int32_t *PP)
+__device__ void wave_one(const EvalArgs &a, int t, long long scen, int32_t *G, int32_t *PP)
 {
     const int lane = threadIdx.x;
-    const int n = a.n;
+    const int64_t ab = tour_abase(a.tour.tptr, t);
+    const int n = (int)(a.tour.tptr[t + 1] - a.tour.tptr[t]);
+    const int64_t *rowoff = a.tour.rowoff + ab;
+    const int32_t *w = a.tour.w + ab;
     const int Q = a.Q;
     const char *dem = reinterpret_cast<const char *>(a.demand + scen);
     const int chunk = (n + 63) / 64;
     const int lo = lane * chunk + 1;
     const int hi = min(lo + chunk - 1, n);
     int local = 0;
-    for (int i = lo; i <= hi; ++i) local += *(const uint16_t *)(dem + a.tour.rowoff[i]);
+    for (int i = lo; i <= hi; ++i) local += *(const uint16_t *)(dem + rowoff[i]);
     int run = wave_exclusive_sum(local);
     for (int i = lo; i <= hi; ++i) {
-        run += *(const uint16_t *)(dem + a.tour.rowoff[i]);
+        run += *(const uint16_t *)(dem + rowoff[i]);
         PP[i] = run;
     }
     if (lane == 0) {
         PP[0] = 0;
-        G[0] = a.tour.w[0];
+        G[0] = w[0];
     }
     __syncthreads();
     int s = 0;
@@ -650,28 +700,47 @@ __device__ void wave_one(const EvalArgs &a, long long scen, int32_t *G, int32_t 
             const int p = base + lane;
             if (p < i) mn = min(mn, G[p]);
         }
-        G[i] = wave_min(mn) + a.tour.w[i];
+        G[i] = wave_min(mn) + w[i];
     }
     if (lane == 0) {
         if (err)
-            atomicOr(&a.stats->err_demand, 1);
+            atomicOr(&a.stats[t].err_demand, 1);
         else
-            a.cost[scen] = G[n];
+            a.cost[(long long)t * a.ldc + scen] = G[n];
     }
     __syncthreads();
 }
 
-// mode 0: scenario k for k = blockIdx.x, blockIdx.x + gridDim.x, ... < S.
-// mode 1: the scenarios queued by the lane kernel.
+// mode 0: every (tour, scenario) pair, k = t * S + s over k = blockIdx.x, blockIdx.x +
+//         gridDim.x, ...
+// mode 1: the pairs the lane kernel marked kCostOvf; a workgroup scans 64 costs of one tour
+//         at a time and evaluates the marked ones. Returns at once when nothing was marked.
 __global__ __launch_bounds__(64) void split_wave_kernel(EvalArgs a, int mode)
 {
     extern __shared__ int32_t lds[];
     int32_t *G = lds;
-    int32_t *PP = lds + (a.n + 1);
-    const long long count = mode == 0 ? a.S : (long long)a.stats->ovf_count;
-    for (long long k = blockIdx.x; k < count; k += gridDim.x) {
-        const long long scen = mode == 0 ? k : (long long)a.ovf_list[k];
-        wave_one(a, scen, G, PP);
+    int32_t *PP = lds + (a.maxn + 1);
+    const long long T = a.tour.T;
+    if (mode == 0) {
+        for (long long k = blockIdx.x; k < T * a.S; k += gridDim.x) {
+            const int t = (int)(k / a.S);
+            wave_one(a, t, k - (long long)t * a.S, G, PP);
+        }
+        return;
+    }
+    if (a.ctl->ovf_total == 0) return;
+    const long long nsb = (a.S + 63) / 64;
+    for (long long k = blockIdx.x; k < T * nsb; k += gridDim.x) {
+        const int t = (int)(k / nsb);
+        const long long s0 = (k - (long long)t * nsb) * 64;
+        const long long scen = s0 + threadIdx.x;
+        const bool marked = scen < a.S && a.cost[(long long)t * a.ldc + scen] == kCostOvf;
+        unsigned long long m = __ballot(marked);
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            wave_one(a, t, s0 + j, G, PP);
+        }
     }
 }
 
@@ -709,35 +778,42 @@ __device__ void block_reduce3(unsigned long long &s, unsigned long long &lo,
     hi = rh[0];
 }
 
+// grid (nblocks, T): workgroup (b, t) sums a strided share of tour t's costs
 __global__ __launch_bounds__(256) void split_moments_partial(MomentArgs a)
 {
+    const int t = blockIdx.y;
+    const int32_t *cost = a.cost + (long long)t * a.ldc;
     unsigned long long s = 0, lo = 0, hi = 0;
     for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < a.S;
          k += (long long)gridDim.x * 256) {
-        const unsigned long long c = (unsigned int)a.cost[k];
+        const unsigned long long c = (unsigned int)cost[k];
         s += c;
         add128(lo, hi, c * c, 0);
     }
     block_reduce3(s, lo, hi);
     if (threadIdx.x == 0) {
-        a.partials[3 * blockIdx.x + 0] = s;
-        a.partials[3 * blockIdx.x + 1] = lo;
-        a.partials[3 * blockIdx.x + 2] = hi;
+        unsigned long long *p = a.partials + 3 * ((long long)t * a.nblocks + blockIdx.x);
+        p[0] = s;
+        p[1] = lo;
+        p[2] = hi;
     }
 }
 
+// grid T: workgroup t combines the partials of tour t
 __global__ __launch_bounds__(256) void split_moments_final(MomentArgs a)
 {
+    const int t = blockIdx.x;
+    const unsigned long long *p = a.partials + 3 * (long long)t * a.nblocks;
     unsigned long long s = 0, lo = 0, hi = 0;
     for (int b = threadIdx.x; b < a.nblocks; b += 256) {
-        s += a.partials[3 * b + 0];
-        add128(lo, hi, a.partials[3 * b + 1], a.partials[3 * b + 2]);
+        s += p[3 * b + 0];
+        add128(lo, hi, p[3 * b + 1], p[3 * b + 2]);
     }
     block_reduce3(s, lo, hi);
     if (threadIdx.x == 0) {
-        a.stats->sum = s;
-        a.stats->sq_lo = lo;
-        a.stats->sq_hi = hi;
+        a.stats[t].sum = s;
+        a.stats[t].sq_lo = lo;
+        a.stats[t].sq_hi = hi;
     }
 }
 
@@ -745,34 +821,45 @@ __global__ __launch_bounds__(256) void split_moments_final(MomentArgs a)
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(split_prep_kernel, dim3(1), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(split_prep_kernel, dim3(a.tour.T), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_lane(const EvalArgs &a, hipStream_t stream)
 {
-    const long long nb = (a.S + 63) / 64;
-    hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)nb), dim3(64), 0, stream,
-                       reinterpret_cast<const char *>(a.demand), a.tour.rowoff32, a.tour.w, a.cost,
-                       a.stats, a.ovf_list, (long long)a.S, a.n, a.Q, a.lane_bytes);
+    hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)a.lane_grid), dim3(64), 0, stream, a);
     return hipGetLastError();
 }
 
-static size_t wave_lds_bytes(int n) { return sizeof(int32_t) * 2 * ((size_t)n + 1); }
+static size_t wave_lds_bytes(int maxn) { return sizeof(int32_t) * 2 * ((size_t)maxn + 1); }
+
+// Dynamic LDS beyond the default 64 KiB (tours near the maximum length) must be opted into.
+static hipError_t wave_lds_allow(size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)split_wave_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 
 hipError_t launch_wave_all(const EvalArgs &a, hipStream_t stream)
 {
-    const long long nb = a.S < 65536 ? a.S : 65536;
-    hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.n),
-                       stream, a, 0);
+    hipError_t e = wave_lds_allow(wave_lds_bytes(a.maxn));
+    if (e != hipSuccess) return e;
+    const long long work = a.S * a.tour.T;
+    const long long nb = work < 65536 ? work : 65536;
+    hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.maxn), stream,
+                       a, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_wave_fallback(const EvalArgs &a, hipStream_t stream)
 {
-    const long long nb = a.S < 2048 ? a.S : 2048;
-    hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.n),
-                       stream, a, 1);
+    hipError_t e = wave_lds_allow(wave_lds_bytes(a.maxn));
+    if (e != hipSuccess) return e;
+    const long long work = (a.S + 63) / 64 * a.tour.T;
+    const long long nb = work < 2048 ? work : 2048;
+    hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.maxn), stream,
+                       a, 1);
     return hipGetLastError();
 }
 
@@ -786,10 +873,10 @@ int32_t moment_blocks(int64_t S)
 
 hipError_t launch_moments(const MomentArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(split_moments_partial, dim3(a.nblocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(split_moments_partial, dim3(a.nblocks, a.T), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(split_moments_final, dim3(1), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(split_moments_final, dim3(a.T), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
