@@ -510,7 +510,9 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
             sNext[kLB - 2] = pair_count<4>(pprev, TT[kLB / 2 - 1] & 0xFFFFu, x);
             sat |= x;
         }
-        lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
+        // no later block reads the last block's records (and its suffix offsets would hold
+        // g_n = f_n, which need not fit 16 bits)
+        if (c < nb) lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
         // the last pair read positions up to its base + 11; the ring is written up to
         // first + 15. Either condition below is rare: redo the block's starts state by state.
         if (__any((int32_t)sat < 0 || (s_of(sNext[kLB - 3]) & ~1) > first + kLB - 12))

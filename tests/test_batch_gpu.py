@@ -152,3 +152,16 @@ def test_batch_argument_errors(ctx):
         with pytest.raises(sg.SplitError) as ei:
             ctx.eval_batch(tours, dem, w.Q)
         assert ei.value.status == code
+
+
+def test_every_tail_length_stays_in_the_lane_kernel(ctx):
+    # short capacity windows (copula demands, mean 20, Q = 500): the lane kernel finishes every
+    # scenario itself whatever n mod 16 is, including a last block that ends at state n
+    b = gen.make_batch_workload("batch-256", T=1, S=1024)
+    d = oracle.dist_matrix(b.xy)
+    lens = [16 * k + r for r, k in zip(range(16), (1, 2, 3, 5, 8, 13, 21, 34, 55, 40, 20, 10,
+                                                    6, 4, 3, 61))]
+    tours = [gen.tour(b.seed, b.N, n, variant=100 + n) for n in lens]
+    print(f"[batch] tail lengths {lens}", flush=True)
+    _, stats = check_batch(ctx, tours, b.demand, b.Q, d, form="lane", xy=b.xy)
+    assert [s.n_fallback for s in stats] == [0] * len(tours)
