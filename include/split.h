@@ -154,6 +154,84 @@ split_status split_batch_stats_get(split_ctx *ctx, split_stats *stats, int32_t *
 split_status split_set_form(split_ctx *ctx, int form);
 
 /*
+ * Launch choices of the evaluations (none changes a result: every choice computes exactly
+ * Section 3's Eqs. (1)-(3)).
+ *  form         split_form; SPLIT_FORM_AUTO takes the wave form up to S = 4096, else the lane form.
+ *  lane_per_cu  lane form: 0 = one workgroup per work item (a tour and 64 of its scenarios);
+ *               1..8 = that many persistent workgroups per compute unit, taking work items
+ *               from a queue.
+ *  order        lane form: 0 = work items of longer tours first, 1 = tours in the given order.
+ *  wave_grid    wave form: workgroups of the launch; 0 = min(T * S, 65536).
+ * The default is {SPLIT_FORM_AUTO, 0, 0, 0}. split_set_form sets `form` alone.
+ */
+typedef struct {
+    int32_t form;
+    int32_t lane_per_cu;
+    int32_t order;
+    int32_t wave_grid;
+} split_tuning;
+
+/* Set / read the context's launch choices. Errors: SPLIT_E_INVAL (a field out of range). */
+split_status split_tuning_set(split_ctx *ctx, const split_tuning *tuning);
+split_status split_tuning_get(split_ctx *ctx, split_tuning *tuning);
+
+/*
+ * Autotuner: times whole evaluations (tour upload, kernels, statistics; HIP events on
+ * hip_stream, `reps` timed calls after one warm-up each) of this batch under the candidate
+ * launch choices, installs the fastest in the context and returns it with its mean
+ * milliseconds (either output may be NULL). Candidates: lane form with lane_per_cu in
+ * {0, 8, 4, 2} and both orders; wave form with wave_grid in {0, 8 per CU} when a run on 256
+ * scenarios, scaled to S, comes within 1.5x of the best lane time. Arguments as in
+ * split_eval_batch; `cost` is overwritten and ends holding the batch's costs under the chosen
+ * tuning, and the context's latest evaluation (split_batch_stats_get) is that one.
+ * Blocks until done. Errors: as split_eval_batch; SPLIT_E_INVAL if reps is not in 1..1000.
+ * The context's tuning is unchanged on error.
+ */
+split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t *tour_ptr,
+                            int32_t T, const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                            int32_t *cost, int64_t ldc, int32_t reps, void *hip_stream,
+                            split_tuning *best, double *best_ms);
+
+/*
+ * Captured evaluation: the whole split_eval_batch sequence (tour upload from pinned host
+ * memory, prep, Split DP, moments, statistics copy) recorded once as a HIP graph for a fixed
+ * demand matrix, cost matrix, S, Q and instance, then replayed with new tours by
+ * split_graph_launch: one graph launch per batch, for search loops that evaluate many batches.
+ * Results are exactly those of split_eval_batch (Section 3, Eqs. (1)-(3)).
+ *  max_T, max_total_n  capacity: at most max_T tours and max_total_n positions per launch.
+ *  demand    DEVICE int16 [N][ld] holding a row for every customer 1..N of the instance.
+ *  cost      DEVICE int32 [max_T][ldc]; each launch writes rows 0..T-1.
+ * The graph copies the context's instance and launch choices at creation (later changes to the
+ * context do not reach it) and owns its device buffers; demand and cost stay the caller's and
+ * must outlive the graph. Launches of one graph must be ordered (one stream, or synchronized).
+ * Errors: as split_eval_batch for the shapes; SPLIT_E_INVAL for a capacity out of range
+ * (1 <= max_T <= max_total_n <= max_T * N, max_T * ceil(S / 64) < 2^31); SPLIT_E_RANGE when
+ * 4 * (N + 1) * max_arc >= 2^31; SPLIT_E_HIP when capture or instantiation fails.
+ */
+typedef struct split_graph split_graph;
+split_status split_graph_create(split_ctx *ctx, int32_t max_T, int64_t max_total_n,
+                                const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                                int32_t *cost, int64_t ldc, split_graph **out);
+
+/*
+ * Stage T tours (HOST arrays as in split_eval_batch; copied into the graph's pinned memory,
+ * after waiting for the launch before the previous one to finish with it) and launch the
+ * graph on hip_stream. Errors: SPLIT_E_INVAL (T or the positions over capacity, a bad tour
+ * length), SPLIT_E_TOUR, SPLIT_E_RANGE, SPLIT_E_HIP. Error messages go to the creating context.
+ */
+split_status split_graph_launch(split_graph *graph, const int32_t *tours,
+                                const int64_t *tour_ptr, int32_t T, void *hip_stream);
+
+/*
+ * Wait for the graph's latest launch and fill stats[0..T-1] and tour_status[0..T-1] (either may
+ * be NULL), as split_batch_stats_get. Returns SPLIT_E_DEMAND if some tour's status is.
+ */
+split_status split_graph_stats(split_graph *graph, split_stats *stats, int32_t *tour_status);
+
+/* Wait for the graph's launches and free it. NULL ok. Destroy graphs before their context. */
+void split_graph_destroy(split_graph *graph);
+
+/*
  * Kernel timing for benchmarks: when enabled, split_eval records HIP events around its
  * dominant kernel on the caller's stream. split_timing_get waits for the last call and
  * returns the accumulated dominant-kernel milliseconds and the number of timed launches

@@ -26,7 +26,8 @@ EXPORTED = [
     "split_ctx_create", "split_ctx_destroy", "split_last_error", "split_instance_set_coords",
     "split_instance_set_dist", "split_eval", "split_stats_get", "split_eval_batch",
     "split_batch_stats_get", "split_set_form", "split_timing_enable", "split_timing_get",
-    "split_timing_reset",
+    "split_timing_reset", "split_tuning_set", "split_tuning_get", "split_autotune",
+    "split_graph_create", "split_graph_launch", "split_graph_stats", "split_graph_destroy",
 ]
 
 
@@ -40,6 +41,27 @@ class SplitStatsC(ctypes.Structure):
     _fields_ = [("sum", ctypes.c_int64), ("sumsq_lo", ctypes.c_uint64),
                 ("sumsq_hi", ctypes.c_uint64), ("mean", ctypes.c_double),
                 ("var", ctypes.c_double), ("n_fallback", ctypes.c_int64)]
+
+
+class SplitTuningC(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("lane_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("wave_grid", ctypes.c_int32)]
+
+
+@dataclass
+class SplitTuning:
+    """Launch choices (split_tuning): none changes a result."""
+    form: int = FORM_AUTO
+    lane_per_cu: int = 0
+    order: int = 0
+    wave_grid: int = 0
+
+    def to_c(self) -> SplitTuningC:
+        return SplitTuningC(self.form, self.lane_per_cu, self.order, self.wave_grid)
+
+    @staticmethod
+    def from_c(c: SplitTuningC) -> "SplitTuning":
+        return SplitTuning(int(c.form), int(c.lane_per_cu), int(c.order), int(c.wave_grid))
 
 
 @dataclass
@@ -82,9 +104,18 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_char_p)]
     lib.split_timing_reset.argtypes = [P]
+    lib.split_tuning_set.argtypes = [P, ctypes.POINTER(SplitTuningC)]
+    lib.split_tuning_get.argtypes = [P, ctypes.POINTER(SplitTuningC)]
+    lib.split_autotune.argtypes = [P, P, P, i32, P, i64, i64, i32, P, i64, i32, P,
+                                   ctypes.POINTER(SplitTuningC), ctypes.POINTER(ctypes.c_double)]
+    lib.split_graph_create.argtypes = [P, i32, i64, P, i64, i64, i32, P, i64, ctypes.POINTER(P)]
+    lib.split_graph_launch.argtypes = [P, P, P, i32, P]
+    lib.split_graph_stats.argtypes = [P, P, P]
+    lib.split_graph_destroy.argtypes = [P]
+    lib.split_graph_destroy.restype = None
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("split_ctx_destroy", "split_last_error"):
+        if name not in ("split_ctx_destroy", "split_last_error", "split_graph_destroy"):
             fn.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -94,6 +125,45 @@ def load_library(path: str = LIB_PATH):
 def _np():
     import numpy as np
     return np
+
+
+def _pack_tours(tours):
+    """Concatenated int32 tours and their int64 offsets [T + 1]."""
+    np = _np()
+    parts = [np.ascontiguousarray(t, dtype=np.int32).ravel() for t in tours]
+    T = len(parts)
+    if T < 1:
+        raise ValueError("need at least one tour")
+    ptr = np.zeros(T + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([p.size for p in parts])
+    flat = np.ascontiguousarray(np.concatenate(parts))
+    return flat, ptr, T
+
+
+def _demand_shape(demand, S, flat, N):
+    """(ld, S) of a CUDA int16 demand tensor [rows, ld], checked against the tours' ids."""
+    import torch
+    if not (isinstance(demand, torch.Tensor) and demand.is_cuda and
+            demand.dtype == torch.int16 and demand.dim() == 2 and demand.stride(1) == 1):
+        raise ValueError("demand must be a CUDA int16 tensor [N, ld] with unit column stride")
+    ld = demand.stride(0)
+    S = demand.shape[1] if S is None else int(S)
+    if S > demand.shape[1]:
+        raise ValueError(f"S={S} exceeds the demand tensor's {demand.shape[1]} columns")
+    # ids above N are the library's to reject (SPLIT_E_TOUR)
+    if flat is not None and flat.size and demand.shape[0] < int(flat.max()) <= N:
+        raise ValueError("the demand tensor has fewer rows than the largest tour customer id")
+    return ld, S
+
+
+def _cost_matrix(cost, T, S, device):
+    import torch
+    if cost is None:
+        return torch.empty((T, max(S, 1)), dtype=torch.int32, device=device)
+    if not (cost.is_cuda and cost.dtype == torch.int32 and cost.dim() == 2 and
+            cost.shape[0] >= T and cost.shape[1] >= S and cost.stride(1) == 1):
+        raise ValueError("cost must be a CUDA int32 tensor [>= T, >= S] with unit column stride")
+    return cost
 
 
 class SplitContext:
@@ -163,17 +233,7 @@ class SplitContext:
         import torch
         np = _np()
         t = np.ascontiguousarray(tour, dtype=np.int32)
-        if not (isinstance(demand, torch.Tensor) and demand.is_cuda and
-                demand.dtype == torch.int16 and demand.dim() == 2 and
-                demand.stride(1) == 1):
-            raise ValueError("demand must be a CUDA int16 tensor [N, ld] with unit column stride")
-        ld = demand.stride(0)
-        S = demand.shape[1] if S is None else int(S)
-        if S > demand.shape[1]:
-            raise ValueError(f"S={S} exceeds the demand tensor's {demand.shape[1]} columns")
-        # ids above N are the library's to reject (SPLIT_E_TOUR)
-        if t.size and demand.shape[0] < int(t.max()) <= self.N:
-            raise ValueError("the demand tensor has fewer rows than the largest tour customer id")
+        ld, S = _demand_shape(demand, S, t, self.N)
         if cost is None:
             cost = torch.empty(max(S, 1), dtype=torch.int32, device=demand.device)
         elif not (cost.is_cuda and cost.dtype == torch.int32 and cost.is_contiguous() and
@@ -202,29 +262,9 @@ class SplitContext:
         """
         import torch
         np = _np()
-        parts = [np.ascontiguousarray(t, dtype=np.int32).ravel() for t in tours]
-        T = len(parts)
-        if T < 1:
-            raise ValueError("need at least one tour")
-        ptr = np.zeros(T + 1, dtype=np.int64)
-        ptr[1:] = np.cumsum([p.size for p in parts])
-        flat = np.ascontiguousarray(np.concatenate(parts) if T else np.zeros(0, np.int32))
-        if not (isinstance(demand, torch.Tensor) and demand.is_cuda and
-                demand.dtype == torch.int16 and demand.dim() == 2 and
-                demand.stride(1) == 1):
-            raise ValueError("demand must be a CUDA int16 tensor [N, ld] with unit column stride")
-        ld = demand.stride(0)
-        S = demand.shape[1] if S is None else int(S)
-        if S > demand.shape[1]:
-            raise ValueError(f"S={S} exceeds the demand tensor's {demand.shape[1]} columns")
-        if flat.size and demand.shape[0] < int(flat.max()) <= self.N:
-            raise ValueError("the demand tensor has fewer rows than the largest tour customer id")
-        if cost is None:
-            cost = torch.empty((T, max(S, 1)), dtype=torch.int32, device=demand.device)
-        elif not (cost.is_cuda and cost.dtype == torch.int32 and cost.dim() == 2 and
-                  cost.shape[0] >= T and cost.shape[1] >= S and cost.stride(1) == 1):
-            raise ValueError("cost must be a CUDA int32 tensor [>= T, >= S] with unit column "
-                             "stride")
+        flat, ptr, T = _pack_tours(tours)
+        ld, S = _demand_shape(demand, S, flat, self.N)
+        cost = _cost_matrix(cost, T, S, demand.device)
         if stream is None:
             stream = torch.cuda.current_stream(demand.device)
         sh = ctypes.c_void_p(stream.cuda_stream)
@@ -240,6 +280,42 @@ class SplitContext:
         if not sync:
             return cost, None, None
         return cost, [self._stats(o) for o in outs], [int(x) for x in status]
+
+    # -- launch choices
+    def tuning(self) -> SplitTuning:
+        c = SplitTuningC()
+        self._check(self._lib.split_tuning_get(self._h, ctypes.byref(c)))
+        return SplitTuning.from_c(c)
+
+    def set_tuning(self, tuning: SplitTuning):
+        c = tuning.to_c()
+        self._check(self._lib.split_tuning_set(self._h, ctypes.byref(c)))
+
+    def autotune(self, tours, demand, Q: int, S: int | None = None, cost=None, reps: int = 3,
+                 stream=None):
+        """Time the candidate launch choices on this batch, install the fastest and return
+        (SplitTuning, mean ms of one evaluation, cost [T, S] of the batch under it)."""
+        import torch
+        flat, ptr, T = _pack_tours(tours)
+        ld, S = _demand_shape(demand, S, flat, self.N)
+        cost = _cost_matrix(cost, T, S, demand.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(demand.device)
+        best = SplitTuningC()
+        ms = ctypes.c_double()
+        self._last_T = T
+        self._check(self._lib.split_autotune(
+            self._h, flat.ctypes.data_as(ctypes.c_void_p), ptr.ctypes.data_as(ctypes.c_void_p),
+            T, ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q), ctypes.c_void_p(cost.data_ptr()),
+            cost.stride(0), int(reps), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best),
+            ctypes.byref(ms)))
+        return SplitTuning.from_c(best), float(ms.value), cost
+
+    def graph(self, max_T: int, max_total_n: int, demand, Q: int, S: int | None = None,
+              cost=None) -> "SplitGraph":
+        """Capture the evaluation of batches of up to max_T tours and max_total_n positions
+        against `demand` into a HIP graph (see SplitGraph)."""
+        return SplitGraph(self, max_T, max_total_n, demand, Q, S, cost)
 
     def batch_stats(self):
         """Statistics and per-tour status of the latest evaluation (waits for it)."""
@@ -276,3 +352,68 @@ class SplitContext:
         self._check(self._lib.split_timing_get(self._h, ctypes.byref(ms), ctypes.byref(n),
                                                ctypes.byref(name)))
         return float(ms.value), int(n.value), (name.value.decode() if name.value else "")
+
+
+class SplitGraph:
+    """A captured evaluation (split_graph_*): fixed demand, cost, S, Q, instance and launch
+    choices; each launch stages new tours and replays one HIP graph. The demand tensor must
+    hold a row for every customer 1..N. Keep the SplitContext alive while the graph is."""
+
+    def __init__(self, ctx: SplitContext, max_T: int, max_total_n: int, demand, Q: int,
+                 S: int | None = None, cost=None):
+        self._ctx = ctx
+        self._lib = ctx._lib
+        ld, S = _demand_shape(demand, S, None, ctx.N)
+        if demand.shape[0] < ctx.N:
+            raise ValueError("the demand tensor needs a row for every customer 1..N")
+        self.cost = _cost_matrix(cost, max_T, S, demand.device)
+        self.demand = demand  # the graph reads it at every launch: keep it alive
+        self.S, self.Q, self.max_T = S, int(Q), int(max_T)
+        self._T = 0
+        h = ctypes.c_void_p()
+        ctx._check(self._lib.split_graph_create(
+            ctx._h, int(max_T), int(max_total_n), ctypes.c_void_p(demand.data_ptr()), S, ld,
+            int(Q), ctypes.c_void_p(self.cost.data_ptr()), self.cost.stride(0), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, tours, stream=None):
+        """Stage `tours` and replay the graph on `stream` (default: the current stream).
+        Returns the cost tensor (rows 0..T-1 are this batch's once the stream reaches them)."""
+        import torch
+        flat, ptr, T = _pack_tours(tours)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.cost.device)
+        self._ctx._check(self._lib.split_graph_launch(
+            self._h, flat.ctypes.data_as(ctypes.c_void_p), ptr.ctypes.data_as(ctypes.c_void_p),
+            T, ctypes.c_void_p(stream.cuda_stream)))
+        self._T = T
+        return self.cost
+
+    def stats(self):
+        """([SplitStats] * T, [status] * T) of the latest launch (waits for it)."""
+        np = _np()
+        T = max(self._T, 1)
+        outs = (SplitStatsC * T)()
+        status = np.zeros(T, dtype=np.int32)
+        st = self._lib.split_graph_stats(self._h, ctypes.cast(outs, ctypes.c_void_p),
+                                         status.ctypes.data_as(ctypes.c_void_p))
+        if st not in (SPLIT_OK, SPLIT_E_DEMAND):
+            self._ctx._check(st)
+        return [SplitContext._stats(o) for o in outs], [int(x) for x in status]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.split_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,5 +1,6 @@
-// C-ABI host layer of libsplitgpu.so: argument checking, device buffers, kernel launches and
-// the conversion of the exact device moments into the sample mean and variance.
+// C-ABI host layer of libsplitgpu.so: argument checking, device buffers, kernel launches, the
+// autotuner, captured evaluation graphs, and the conversion of the exact device moments into
+// the sample mean and variance.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -7,8 +8,8 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <string>
 #include <algorithm>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -22,42 +23,104 @@ namespace {
 constexpr int kStages = 8;              // pinned host slots for tour uploads
 constexpr int64_t kWaveAutoMaxS = 4096;  // SPLIT_FORM_AUTO uses the wave form up to this S
 constexpr int kMaxTimingPairs = 4096;
+constexpr int kGraphSlots = 2;          // a graph's launches alternate between two host slots
+constexpr int32_t kMaxLanePerCu = 8;    // the lane kernel's LDS allows 8 workgroups per CU
 
-}  // namespace
+// Device buffers of one evaluation sequence. The context's grow with its calls; a graph owns
+// a fixed set.
+struct EvalBuffers {
+    char *d_stage = nullptr;  // staged header, see TourDev
+    int64_t cap_stage = 0;
+    int64_t *d_rowoff = nullptr;
+    uint32_t *d_rowoff32 = nullptr;
+    int32_t *d_w = nullptr;
+    int64_t cap_pos = 0;      // entries of the per-tour arrays
+    DevStats *d_stats = nullptr;
+    int32_t cap_T = 0;
+    unsigned long long *d_partials = nullptr;
+    int64_t cap_partials = 0;
+    BatchCtl *d_ctl = nullptr;
+};
 
-struct split_ctx {
-    int device = 0;
-    std::string err;
-    int form = SPLIT_FORM_AUTO;
+void free_buffers(EvalBuffers &b)
+{
+    if (b.d_stage) (void)hipFree(b.d_stage);
+    if (b.d_rowoff) (void)hipFree(b.d_rowoff);
+    if (b.d_rowoff32) (void)hipFree(b.d_rowoff32);
+    if (b.d_w) (void)hipFree(b.d_w);
+    if (b.d_stats) (void)hipFree(b.d_stats);
+    if (b.d_partials) (void)hipFree(b.d_partials);
+    if (b.d_ctl) (void)hipFree(b.d_ctl);
+    b = EvalBuffers();
+}
 
-    // instance
+// Byte offsets of the staged header for capacity capT tours and cap_n positions:
+// int64 T at 0, int64 tptr[capT + 1] at 8, int32 order[capT], int32 tours[cap_n].
+struct StageLayout {
+    int32_t capT = 0;
+    size_t off_order = 0, off_tours = 0, bytes = 0;
+};
+
+StageLayout stage_layout(int32_t capT, int64_t cap_n)
+{
+    StageLayout L;
+    L.capT = capT;
+    L.off_order = sizeof(int64_t) * (2 + (size_t)capT);
+    L.off_tours = L.off_order + ((sizeof(int32_t) * (size_t)capT + 7) & ~(size_t)7);
+    L.bytes = L.off_tours + sizeof(int32_t) * (size_t)cap_n;
+    return L;
+}
+
+// Summary of a validated batch.
+struct BatchInfo {
+    int32_t T = 0, max_id = 0, maxn = 0;
+    int64_t total_n = 0;
+};
+
+// What the kernels of one evaluation are launched with.
+struct Plan {
+    int form = SPLIT_FORM_LANE;
+    int32_t lane_grid = 0, wave_grid = 0, maxn = 0;
+    uint32_t lane_bytes = 0;
+};
+
+// The instance as the kernels see it (a graph keeps its own copy).
+struct Instance {
     int32_t N = 0;
     int kind = -1;  // 0 coordinates, 1 matrix
     int32_t *d_xy = nullptr;
     int32_t *d_dist = nullptr;
     int64_t max_arc = 0;
+};
+
+void free_instance(Instance &in)
+{
+    if (in.d_xy) (void)hipFree(in.d_xy);
+    if (in.d_dist) (void)hipFree(in.d_dist);
+    in = Instance();
+}
+
+}  // namespace
+
+struct split_ctx {
+    int device = 0;
+    int cus = 0;
+    std::string err;
+    split_tuning tuning = {SPLIT_FORM_AUTO, 0, 0, 0};
+
+    Instance inst;
     std::vector<unsigned char> seen;
 
-    // per-call device buffers, sized for the largest batch seen
-    char *d_stage = nullptr;           // tours, tour offsets and work order of the call
-    int64_t *d_rowoff = nullptr;
-    uint32_t *d_rowoff32 = nullptr;
-    int32_t *d_w = nullptr;
-    int64_t cap_pos = 0;               // entries of the per-tour arrays
-    int64_t cap_stage = 0;             // bytes of the staging buffers
-    int32_t cap_T = 0;                 // tours
-    unsigned long long *d_partials = nullptr;
-    int64_t cap_partials = 0;
-    DevStats *d_stats = nullptr;
-    BatchCtl *d_ctl = nullptr;
-    int lane_grid = 0;                 // persistent workgroups of the lane kernel
+    EvalBuffers buf;
 
     // pinned host staging
     char *h_stage[kStages] = {};
+    int64_t cap_h_stage = 0;
     hipEvent_t stage_ev[kStages] = {};
     bool stage_ev_used[kStages] = {};
     int stage = 0;
     DevStats *h_stats = nullptr;
+    int32_t cap_h_stats = 0;
     hipEvent_t stats_ev = nullptr;
     bool have_call = false;
     int64_t last_S = 0;
@@ -70,6 +133,30 @@ struct split_ctx {
     double ms_acc = 0.0;
     int64_t launches = 0;
     const char *tname = "";
+};
+
+struct split_graph {
+    split_ctx *ctx = nullptr;  // for error messages and the device
+    Instance inst;
+    std::vector<unsigned char> seen;
+    EvalBuffers buf;
+    StageLayout layout;
+    int32_t max_T = 0;
+    int64_t max_total_n = 0;
+    int64_t S = 0, ld = 0, ldc = 0;
+    int32_t Q = 0;
+    int order = 0;
+    Plan plan;
+    hipStream_t cap_stream = nullptr;
+    char *h_stage[kGraphSlots] = {};
+    DevStats *h_stats[kGraphSlots] = {};
+    hipGraph_t graph[kGraphSlots] = {};
+    hipGraphExec_t exec[kGraphSlots] = {};
+    hipEvent_t done[kGraphSlots] = {};
+    bool used[kGraphSlots] = {};
+    int next = 0;
+    int last = -1;
+    int32_t last_T = 0;
 };
 
 namespace {
@@ -113,17 +200,6 @@ struct DeviceGuard {
     }
 };
 
-void free_instance(split_ctx *ctx)
-{
-    if (ctx->d_xy) (void)hipFree(ctx->d_xy);
-    if (ctx->d_dist) (void)hipFree(ctx->d_dist);
-    ctx->d_xy = nullptr;
-    ctx->d_dist = nullptr;
-    ctx->N = 0;
-    ctx->kind = -1;
-    ctx->max_arc = 0;
-}
-
 template <class P>
 bool grow(P **ptr, size_t bytes)
 {
@@ -132,30 +208,62 @@ bool grow(P **ptr, size_t bytes)
     return hipMalloc(ptr, bytes) == hipSuccess;
 }
 
-// Buffers for a batch of T tours with total_n positions, staging of stage_bytes and
-// moment partials of T * nblocks blocks. Waits for enqueued work before replacing a buffer.
-split_status ensure_capacity(split_ctx *ctx, int32_t T, int64_t total_n, int64_t stage_bytes,
-                             int64_t partial_blocks)
+// Device buffers for T tours with total_n positions in all, staging of stage_bytes and moment
+// partials of partial_blocks blocks (exact sizes, or with room to grow). Growing waits for
+// enqueued work before replacing a buffer.
+split_status ensure_buffers(split_ctx *ctx, EvalBuffers &b, int32_t T, int64_t total_n,
+                            int64_t stage_bytes, int64_t partial_blocks, bool exact)
 {
     const int64_t pos = total_n + (int64_t)T * (1 + kRowPad);
-    const bool g_pos = pos > ctx->cap_pos, g_stage = stage_bytes > ctx->cap_stage;
-    const bool g_T = T > ctx->cap_T, g_part = partial_blocks > ctx->cap_partials;
-    if (!g_pos && !g_stage && !g_T && !g_part) return SPLIT_OK;
+    const bool g_pos = pos > b.cap_pos, g_stage = stage_bytes > b.cap_stage;
+    const bool g_T = T > b.cap_T, g_part = partial_blocks > b.cap_partials;
+    const bool g_ctl = b.d_ctl == nullptr;
+    if (!g_pos && !g_stage && !g_T && !g_part && !g_ctl) return SPLIT_OK;
     HIP_TRY(ctx, hipDeviceSynchronize());
+    auto room = [exact](int64_t need, int64_t floor) {
+        return exact ? need : (need < floor ? floor : need + need / 4);
+    };
     if (g_pos) {
-        const int64_t np = pos < 4096 ? 4096 : pos + pos / 4;
-        ctx->cap_pos = 0;
-        if (!grow(&ctx->d_rowoff, sizeof(int64_t) * np) ||
-            !grow(&ctx->d_rowoff32, sizeof(uint32_t) * np) || !grow(&ctx->d_w, sizeof(int32_t) * np))
+        const int64_t np = room(pos, 4096);
+        b.cap_pos = 0;
+        if (!grow(&b.d_rowoff, sizeof(int64_t) * np) ||
+            !grow(&b.d_rowoff32, sizeof(uint32_t) * np) || !grow(&b.d_w, sizeof(int32_t) * np))
             return fail(ctx, SPLIT_E_NOMEM, "device allocation for %lld tour positions failed",
                         (long long)np);
-        ctx->cap_pos = np;
+        b.cap_pos = np;
     }
     if (g_stage) {
-        const int64_t nb = stage_bytes < 65536 ? 65536 : stage_bytes + stage_bytes / 4;
-        ctx->cap_stage = 0;
-        if (!grow(&ctx->d_stage, (size_t)nb))
+        const int64_t nb = room(stage_bytes, 65536);
+        b.cap_stage = 0;
+        if (!grow(&b.d_stage, (size_t)nb))
             return fail(ctx, SPLIT_E_NOMEM, "device staging of %lld bytes failed", (long long)nb);
+        b.cap_stage = nb;
+    }
+    if (g_T) {
+        const int32_t nt = exact ? T : (T < 16 ? 16 : T);
+        b.cap_T = 0;
+        if (!grow(&b.d_stats, sizeof(DevStats) * nt))
+            return fail(ctx, SPLIT_E_NOMEM, "allocation of %d result blocks failed", nt);
+        b.cap_T = nt;
+    }
+    if (g_part) {
+        b.cap_partials = 0;
+        if (!grow(&b.d_partials, sizeof(unsigned long long) * 3 * partial_blocks))
+            return fail(ctx, SPLIT_E_NOMEM, "allocation of moment partials failed");
+        b.cap_partials = partial_blocks;
+    }
+    if (g_ctl && hipMalloc(&b.d_ctl, sizeof(BatchCtl)) != hipSuccess)
+        return fail(ctx, SPLIT_E_NOMEM, "allocation of the batch counters failed");
+    return SPLIT_OK;
+}
+
+// Pinned host staging of the context: kStages slots of stage_bytes and T result blocks.
+split_status ensure_host(split_ctx *ctx, int64_t stage_bytes, int32_t T)
+{
+    if (stage_bytes > ctx->cap_h_stage) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        const int64_t nb = stage_bytes < 65536 ? 65536 : stage_bytes + stage_bytes / 4;
+        ctx->cap_h_stage = 0;
         for (int k = 0; k < kStages; ++k) {
             if (ctx->h_stage[k]) (void)hipHostFree(ctx->h_stage[k]);
             ctx->h_stage[k] = nullptr;
@@ -164,24 +272,18 @@ split_status ensure_capacity(split_ctx *ctx, int32_t T, int64_t total_n, int64_t
                 return fail(ctx, SPLIT_E_NOMEM, "pinned staging of %lld bytes failed",
                             (long long)nb);
         }
-        ctx->cap_stage = nb;
+        ctx->cap_h_stage = nb;
     }
-    if (g_T) {
+    if (T > ctx->cap_h_stats) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
         const int32_t nt = T < 16 ? 16 : T;
-        ctx->cap_T = 0;
         if (ctx->h_stats) (void)hipHostFree(ctx->h_stats);
         ctx->h_stats = nullptr;
-        if (!grow(&ctx->d_stats, sizeof(DevStats) * nt) ||
-            hipHostMalloc((void **)&ctx->h_stats, sizeof(DevStats) * nt, 0) != hipSuccess)
-            return fail(ctx, SPLIT_E_NOMEM, "allocation of %d result blocks failed", nt);
+        ctx->cap_h_stats = 0;
+        if (hipHostMalloc((void **)&ctx->h_stats, sizeof(DevStats) * nt, 0) != hipSuccess)
+            return fail(ctx, SPLIT_E_NOMEM, "pinned allocation of %d result blocks failed", nt);
         memset(ctx->h_stats, 0, sizeof(DevStats) * nt);
-        ctx->cap_T = nt;
-    }
-    if (g_part) {
-        ctx->cap_partials = 0;
-        if (!grow(&ctx->d_partials, sizeof(unsigned long long) * 3 * partial_blocks))
-            return fail(ctx, SPLIT_E_NOMEM, "allocation of moment partials failed");
-        ctx->cap_partials = partial_blocks;
+        ctx->cap_h_stats = nt;
     }
     return SPLIT_OK;
 }
@@ -236,6 +338,241 @@ void fill_stats(const DevStats &d, int64_t S, split_stats *out)
     out->n_fallback = d.ovf_count;
 }
 
+// Per-tour statistics and status of T result blocks; SPLIT_E_DEMAND names the first bad tour.
+split_status report(split_ctx *ctx, const DevStats *h, int32_t T, int64_t S, split_stats *stats,
+                    int32_t *tour_status)
+{
+    int bad = -1;
+    for (int32_t t = 0; t < T; ++t) {
+        if (stats) fill_stats(h[t], S, stats + t);
+        if (tour_status) tour_status[t] = h[t].err_demand ? SPLIT_E_DEMAND : SPLIT_OK;
+        if (h[t].err_demand && bad < 0) bad = t;
+    }
+    if (bad >= 0)
+        return fail(ctx, SPLIT_E_DEMAND, "tour %d: a scenario has a demand q < 0 or q > Q on the "
+                    "tour", bad);
+    return SPLIT_OK;
+}
+
+split_status check_shape(split_ctx *ctx, const char *who, int64_t S, int64_t ld, int32_t Q,
+                         int64_t ldc)
+{
+    if (S < 1 || S > INT32_MAX || ld < S || ldc < S)
+        return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= S < 2^31, ld >= S and ldc >= S", who);
+    if (Q < 1 || Q > 16383) return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= Q <= 16383", who);
+    return SPLIT_OK;
+}
+
+// Tours against instance `in` (seen: scratch of N + 1 zeros, left zeroed), the work-item
+// bound T * ceil(S / 64) < 2^31 and the int32 range of the DP.
+split_status check_tours(split_ctx *ctx, const char *who, const Instance &in,
+                         std::vector<unsigned char> &seen, const int32_t *tours,
+                         const int64_t *tour_ptr, int32_t T, int64_t S, BatchInfo *info)
+{
+    if (!tours || !tour_ptr) return fail(ctx, SPLIT_E_INVAL, "%s: NULL pointer", who);
+    if (T < 1) return fail(ctx, SPLIT_E_INVAL, "%s: need T >= 1", who);
+    if (tour_ptr[0] != 0) return fail(ctx, SPLIT_E_INVAL, "%s: tour_ptr[0] must be 0", who);
+    BatchInfo bi;
+    bi.T = T;
+    for (int32_t t = 0; t < T; ++t) {
+        const int64_t n64 = tour_ptr[t + 1] - tour_ptr[t];
+        if (n64 < 1 || n64 > in.N)
+            return fail(ctx, SPLIT_E_INVAL, "%s: tour %d has length %lld (need 1..N)", who, t,
+                        (long long)n64);
+        const int32_t n = (int32_t)n64;
+        bi.maxn = n > bi.maxn ? n : bi.maxn;
+        const int32_t *tour = tours + tour_ptr[t];
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t c = tour[k];
+            if (c < 1 || c > in.N || seen[c]) {
+                for (int32_t j = 0; j < k; ++j) seen[tour[j]] = 0;
+                return fail(ctx, SPLIT_E_TOUR, "%s: tour %d position %d: id %d is out of range "
+                            "or repeated", who, t, k, c);
+            }
+            seen[c] = 1;
+            bi.max_id = c > bi.max_id ? c : bi.max_id;
+        }
+        for (int32_t k = 0; k < n; ++k) seen[tour[k]] = 0;
+    }
+    bi.total_n = tour_ptr[T];
+    const int64_t nsb = (S + 63) / 64;
+    if ((__int128)nsb * T >= ((__int128)1 << 31))
+        return fail(ctx, SPLIT_E_INVAL, "%s: T * ceil(S / 64) must be below 2^31", who);
+    // |g| and |w| stay below (2n+3) * max_arc; keep them below 2^30 with a margin.
+    if ((__int128)4 * ((__int128)bi.maxn + 1) * in.max_arc >= ((__int128)1 << 31))
+        return fail(ctx, SPLIT_E_RANGE, "%s: 4*(n+1)*max_arc = 4*%d*%lld exceeds 2^31", who,
+                    bi.maxn + 1, (long long)in.max_arc);
+    *info = bi;
+    return SPLIT_OK;
+}
+
+// Header, work order and tours into host memory h laid out by L (T <= L.capT).
+void stage_write(char *h, const StageLayout &L, const int32_t *tours, const int64_t *tour_ptr,
+                 int32_t T, int order_mode)
+{
+    const int64_t T64 = T;
+    memcpy(h, &T64, sizeof T64);
+    memcpy(h + sizeof(int64_t), tour_ptr, sizeof(int64_t) * ((size_t)T + 1));
+    int32_t *order = reinterpret_cast<int32_t *>(h + L.off_order);
+    for (int32_t t = 0; t < T; ++t) order[t] = t;
+    if (order_mode == 0) {
+        // longest tours first (ties by index), so that short ones fill the tail
+        std::stable_sort(order, order + T, [&](int32_t x, int32_t y) {
+            return tour_ptr[x + 1] - tour_ptr[x] > tour_ptr[y + 1] - tour_ptr[y];
+        });
+    }
+    memcpy(h + L.off_tours, tours, sizeof(int32_t) * (size_t)tour_ptr[T]);
+}
+
+// Launch configuration from the tuning. T_grid bounds T; maxn and max_id bound the tours.
+Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t ld,
+               int32_t T_grid, int32_t maxn, int32_t max_id)
+{
+    Plan p;
+    p.form = tu.form;
+    if (p.form == SPLIT_FORM_AUTO) p.form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
+    // the lane kernel addresses demands with 32-bit buffer offsets
+    const __int128 lane_bytes = ((__int128)(max_id - 1) * ld + S) * 2;
+    const bool lane_addressable = lane_bytes <= (__int128)kRowAbsent;
+    p.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
+    if (p.form == SPLIT_FORM_LANE && !lane_addressable) p.form = SPLIT_FORM_WAVE;
+    const int64_t items = (S + 63) / 64 * T_grid;
+    const int64_t lg = tu.lane_per_cu <= 0 ? items : (int64_t)ctx->cus * tu.lane_per_cu;
+    p.lane_grid = (int32_t)(lg < items ? lg : items);
+    p.wave_grid = tu.wave_grid > 0 ? tu.wave_grid : 65536;
+    p.maxn = maxn;
+    return p;
+}
+
+// The kernels of one evaluation on `stream`, reading the header already staged in b.d_stage
+// (laid out by L): prep, the Split DP (lane kernel and its fallback, or the wave kernel),
+// moments. The dominant kernel is timed when ctx->timing and `timed` are set.
+split_status enqueue_kernels(split_ctx *ctx, const Instance &in, const EvalBuffers &b,
+                             const StageLayout &L, const Plan &p, const int16_t *demand,
+                             int64_t S, int64_t ld, int32_t Q, int32_t *cost, int64_t ldc,
+                             hipStream_t stream, bool timed)
+{
+    TourDev td;
+    td.nt = reinterpret_cast<const int64_t *>(b.d_stage);
+    td.tptr = td.nt + 1;
+    td.order = reinterpret_cast<const int32_t *>(b.d_stage + L.off_order);
+    td.tours = reinterpret_cast<const int32_t *>(b.d_stage + L.off_tours);
+    td.T_grid = L.capT;
+    td.rowoff = b.d_rowoff;
+    td.rowoff32 = b.d_rowoff32;
+    td.w = b.d_w;
+
+    PrepArgs pa;
+    pa.tour = td;
+    pa.N = in.N;
+    pa.kind = in.kind;
+    pa.xy = in.d_xy;
+    pa.dist = in.d_dist;
+    pa.ld = ld;
+    pa.stats = b.d_stats;
+    pa.ctl = b.d_ctl;
+    HIP_TRY(ctx, launch_prep(pa, stream));
+
+    EvalArgs ea;
+    ea.demand = reinterpret_cast<const uint16_t *>(demand);
+    ea.ld = ld;
+    ea.S = S;
+    ea.Q = Q;
+    ea.tour = td;
+    ea.cost = cost;
+    ea.ldc = ldc;
+    ea.stats = b.d_stats;
+    ea.ctl = b.d_ctl;
+    ea.lane_bytes = p.lane_bytes;
+    ea.lane_grid = p.lane_grid;
+    ea.wave_grid = p.wave_grid;
+    ea.maxn = p.maxn;
+
+    hipEvent_t stop = nullptr;
+    if (timed) {
+        split_status st = timing_begin(ctx, stream, &stop);
+        if (st != SPLIT_OK) return st;
+    }
+    if (p.form == SPLIT_FORM_WAVE) {
+        ctx->tname = wave_kernel_name();
+        HIP_TRY(ctx, launch_wave_all(ea, stream));
+        if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
+    } else {
+        ctx->tname = lane_kernel_name();
+        HIP_TRY(ctx, launch_lane(ea, stream));
+        if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
+        HIP_TRY(ctx, launch_wave_fallback(ea, stream));
+    }
+
+    MomentArgs ma;
+    ma.cost = cost;
+    ma.ldc = ldc;
+    ma.S = S;
+    ma.nt = td.nt;
+    ma.T_grid = L.capT;
+    ma.partials = b.d_partials;
+    ma.nblocks = moment_blocks(S);
+    ma.stats = b.d_stats;
+    HIP_TRY(ctx, launch_moments(ma, stream));
+    return SPLIT_OK;
+}
+
+// The common path of split_eval and split_eval_batch on the context's own buffers.
+split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
+                        const int64_t *tour_ptr, int32_t T, const int16_t *demand, int64_t S,
+                        int64_t ld, int32_t Q, int32_t *cost, int64_t ldc, hipStream_t stream)
+{
+    if (ctx->inst.kind < 0) return fail(ctx, SPLIT_E_INVAL, "%s: no instance set", who);
+    if (!demand || !cost) return fail(ctx, SPLIT_E_INVAL, "%s: NULL pointer", who);
+    split_status st = check_shape(ctx, who, S, ld, Q, ldc);
+    if (st != SPLIT_OK) return st;
+    BatchInfo bi;
+    st = check_tours(ctx, who, ctx->inst, ctx->seen, tours, tour_ptr, T, S, &bi);
+    if (st != SPLIT_OK) return st;
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
+    const StageLayout L = stage_layout(T, bi.total_n);
+    const int32_t nblk = moment_blocks(S);
+    st = ensure_buffers(ctx, ctx->buf, T, bi.total_n, (int64_t)L.bytes, (int64_t)nblk * T, false);
+    if (st != SPLIT_OK) return st;
+    st = ensure_host(ctx, (int64_t)L.bytes, T);
+    if (st != SPLIT_OK) return st;
+
+    // Upload through a pinned slot, reused only after its previous copy completed.
+    const int slot = ctx->stage;
+    ctx->stage = (ctx->stage + 1) % kStages;
+    if (ctx->stage_ev_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->stage_ev[slot]));
+    stage_write(ctx->h_stage[slot], L, tours, tour_ptr, T, ctx->tuning.order);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->buf.d_stage, ctx->h_stage[slot], L.bytes,
+                                hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[slot], stream));
+    ctx->stage_ev_used[slot] = true;
+
+    const Plan p = make_plan(ctx, ctx->tuning, S, ld, T, bi.maxn, bi.max_id);
+    st = enqueue_kernels(ctx, ctx->inst, ctx->buf, L, p, demand, S, ld, Q, cost, ldc, stream, true);
+    if (st != SPLIT_OK) return st;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_stats, ctx->buf.d_stats, sizeof(DevStats) * (size_t)T,
+                                hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->stats_ev, stream));
+    ctx->have_call = true;
+    ctx->last_S = S;
+    ctx->last_T = T;
+    return SPLIT_OK;
+}
+
+split_status check_tuning(split_ctx *ctx, const split_tuning &t)
+{
+    if (t.form != SPLIT_FORM_AUTO && t.form != SPLIT_FORM_LANE && t.form != SPLIT_FORM_WAVE)
+        return fail(ctx, SPLIT_E_INVAL, "tuning: unknown form %d", t.form);
+    if (t.lane_per_cu < 0 || t.lane_per_cu > kMaxLanePerCu)
+        return fail(ctx, SPLIT_E_INVAL, "tuning: lane_per_cu must be in 0..%d", kMaxLanePerCu);
+    if (t.order != 0 && t.order != 1)
+        return fail(ctx, SPLIT_E_INVAL, "tuning: order must be 0 or 1");
+    if (t.wave_grid < 0) return fail(ctx, SPLIT_E_INVAL, "tuning: wave_grid must be >= 0");
+    return SPLIT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -253,13 +590,11 @@ split_status split_ctx_create(int hip_device, split_ctx **out)
     DeviceGuard g(hip_device);
     hipDeviceProp_t prop;
     if (!g.ok || hipGetDeviceProperties(&prop, hip_device) != hipSuccess ||
-        hipMalloc(&ctx->d_ctl, sizeof(BatchCtl)) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->stats_ev, hipEventDisableTiming) != hipSuccess) {
         split_ctx_destroy(ctx);
         return SPLIT_E_NOMEM;
     }
-    // the lane kernel's LDS allows 8 workgroups per CU
-    ctx->lane_grid = prop.multiProcessorCount * 8;
+    ctx->cus = prop.multiProcessorCount;
     for (int k = 0; k < kStages; ++k) {
         if (hipEventCreateWithFlags(&ctx->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
             split_ctx_destroy(ctx);
@@ -276,14 +611,8 @@ void split_ctx_destroy(split_ctx *ctx)
     {
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
-        free_instance(ctx);
-        if (ctx->d_stage) (void)hipFree(ctx->d_stage);
-        if (ctx->d_rowoff) (void)hipFree(ctx->d_rowoff);
-        if (ctx->d_rowoff32) (void)hipFree(ctx->d_rowoff32);
-        if (ctx->d_w) (void)hipFree(ctx->d_w);
-        if (ctx->d_partials) (void)hipFree(ctx->d_partials);
-        if (ctx->d_stats) (void)hipFree(ctx->d_stats);
-        if (ctx->d_ctl) (void)hipFree(ctx->d_ctl);
+        free_instance(ctx->inst);
+        free_buffers(ctx->buf);
         for (int k = 0; k < kStages; ++k) {
             if (ctx->h_stage[k]) (void)hipHostFree(ctx->h_stage[k]);
             if (ctx->stage_ev[k]) (void)hipEventDestroy(ctx->stage_ev[k]);
@@ -321,14 +650,14 @@ split_status split_instance_set_coords(split_ctx *ctx, int32_t N, const int32_t 
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
     HIP_TRY(ctx, hipDeviceSynchronize());
-    free_instance(ctx);
-    HIP_TRY(ctx, hipMalloc(&ctx->d_xy, sizeof(int32_t) * 2 * ((size_t)N + 1)));
-    HIP_TRY(ctx, hipMemcpy(ctx->d_xy, xy, sizeof(int32_t) * 2 * ((size_t)N + 1),
+    free_instance(ctx->inst);
+    HIP_TRY(ctx, hipMalloc(&ctx->inst.d_xy, sizeof(int32_t) * 2 * ((size_t)N + 1)));
+    HIP_TRY(ctx, hipMemcpy(ctx->inst.d_xy, xy, sizeof(int32_t) * 2 * ((size_t)N + 1),
                            hipMemcpyHostToDevice));
     const double dx = (double)(hi[0] - lo[0]), dy = (double)(hi[1] - lo[1]);
-    ctx->max_arc = (int64_t)ceil(sqrt(dx * dx + dy * dy)) + 1;  // bound on any rounded distance
-    ctx->N = N;
-    ctx->kind = 0;
+    ctx->inst.max_arc = (int64_t)ceil(sqrt(dx * dx + dy * dy)) + 1;  // bound on any rounded distance
+    ctx->inst.N = N;
+    ctx->inst.kind = 0;
     ctx->seen.assign((size_t)N + 1, 0);
     return SPLIT_OK;
 }
@@ -347,170 +676,15 @@ split_status split_instance_set_dist(split_ctx *ctx, int32_t N, const int32_t *d
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
     HIP_TRY(ctx, hipDeviceSynchronize());
-    free_instance(ctx);
-    HIP_TRY(ctx, hipMalloc(&ctx->d_dist, sizeof(int32_t) * V * V));
-    HIP_TRY(ctx, hipMemcpy(ctx->d_dist, d, sizeof(int32_t) * V * V, hipMemcpyHostToDevice));
-    ctx->max_arc = mx;
-    ctx->N = N;
-    ctx->kind = 1;
+    free_instance(ctx->inst);
+    HIP_TRY(ctx, hipMalloc(&ctx->inst.d_dist, sizeof(int32_t) * V * V));
+    HIP_TRY(ctx, hipMemcpy(ctx->inst.d_dist, d, sizeof(int32_t) * V * V, hipMemcpyHostToDevice));
+    ctx->inst.max_arc = mx;
+    ctx->inst.N = N;
+    ctx->inst.kind = 1;
     ctx->seen.assign(V, 0);
     return SPLIT_OK;
 }
-
-}  // extern "C"
-
-namespace {
-
-// The common path of split_eval and split_eval_batch.
-split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
-                        const int64_t *tour_ptr, int32_t T, const int16_t *demand, int64_t S,
-                        int64_t ld, int32_t Q, int32_t *cost, int64_t ldc, hipStream_t stream)
-{
-    if (ctx->kind < 0) return fail(ctx, SPLIT_E_INVAL, "%s: no instance set", who);
-    if (!tours || !tour_ptr || !demand || !cost)
-        return fail(ctx, SPLIT_E_INVAL, "%s: NULL pointer", who);
-    if (T < 1) return fail(ctx, SPLIT_E_INVAL, "%s: need T >= 1", who);
-    if (S < 1 || S > INT32_MAX || ld < S || ldc < S)
-        return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= S < 2^31, ld >= S and ldc >= S", who);
-    if (Q < 1 || Q > 16383) return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= Q <= 16383", who);
-    if (tour_ptr[0] != 0) return fail(ctx, SPLIT_E_INVAL, "%s: tour_ptr[0] must be 0", who);
-    int32_t max_id = 0, maxn = 0;
-    for (int32_t t = 0; t < T; ++t) {
-        const int64_t n64 = tour_ptr[t + 1] - tour_ptr[t];
-        if (n64 < 1 || n64 > ctx->N)
-            return fail(ctx, SPLIT_E_INVAL, "%s: tour %d has length %lld (need 1..N)", who, t,
-                        (long long)n64);
-        const int32_t n = (int32_t)n64;
-        maxn = n > maxn ? n : maxn;
-        const int32_t *tour = tours + tour_ptr[t];
-        for (int32_t k = 0; k < n; ++k) {
-            const int32_t c = tour[k];
-            if (c < 1 || c > ctx->N || ctx->seen[c]) {
-                for (int32_t j = 0; j < k; ++j) ctx->seen[tour[j]] = 0;
-                return fail(ctx, SPLIT_E_TOUR, "%s: tour %d position %d: id %d is out of range "
-                            "or repeated", who, t, k, c);
-            }
-            ctx->seen[c] = 1;
-            max_id = c > max_id ? c : max_id;
-        }
-        for (int32_t k = 0; k < n; ++k) ctx->seen[tour[k]] = 0;
-    }
-    const int64_t total_n = tour_ptr[T];
-    const int64_t nsb = (S + 63) / 64;
-    if ((__int128)nsb * T >= ((__int128)1 << 31))
-        return fail(ctx, SPLIT_E_INVAL, "%s: T * ceil(S / 64) must be below 2^31", who);
-    // |g| and |w| stay below (2n+3) * max_arc; keep them below 2^30 with a margin.
-    if ((__int128)4 * ((__int128)maxn + 1) * ctx->max_arc >= ((__int128)1 << 31))
-        return fail(ctx, SPLIT_E_RANGE, "%s: 4*(n+1)*max_arc = 4*%d*%lld exceeds 2^31", who,
-                    maxn + 1, (long long)ctx->max_arc);
-
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
-    // staging layout: tour offsets [T+1] int64, work order [T] int32, tours [total_n] int32
-    const size_t off_order = sizeof(int64_t) * ((size_t)T + 1);
-    const size_t off_tours = off_order + ((sizeof(int32_t) * (size_t)T + 7) & ~(size_t)7);
-    const size_t stage_bytes = off_tours + sizeof(int32_t) * (size_t)total_n;
-    const int32_t nblk = moment_blocks(S);
-    split_status st = ensure_capacity(ctx, T, total_n, (int64_t)stage_bytes, (int64_t)nblk * T);
-    if (st != SPLIT_OK) return st;
-
-    // Upload through a pinned slot, reused only after its previous copy completed.
-    const int slot = ctx->stage;
-    ctx->stage = (ctx->stage + 1) % kStages;
-    if (ctx->stage_ev_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->stage_ev[slot]));
-    char *h = ctx->h_stage[slot];
-    memcpy(h, tour_ptr, sizeof(int64_t) * ((size_t)T + 1));
-    {
-        // work order: longest tours first (ties by index), so short ones fill the tail
-        int32_t *order = reinterpret_cast<int32_t *>(h + off_order);
-        std::vector<int32_t> idx((size_t)T);
-        for (int32_t t = 0; t < T; ++t) idx[t] = t;
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
-            return tour_ptr[x + 1] - tour_ptr[x] > tour_ptr[y + 1] - tour_ptr[y];
-        });
-        memcpy(order, idx.data(), sizeof(int32_t) * (size_t)T);
-    }
-    memcpy(h + off_tours, tours, sizeof(int32_t) * (size_t)total_n);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_stage, h, stage_bytes, hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[slot], stream));
-    ctx->stage_ev_used[slot] = true;
-
-    TourDev td;
-    td.tptr = reinterpret_cast<const int64_t *>(ctx->d_stage);
-    td.order = reinterpret_cast<const int32_t *>(ctx->d_stage + off_order);
-    td.tours = reinterpret_cast<const int32_t *>(ctx->d_stage + off_tours);
-    td.T = T;
-    td.rowoff = ctx->d_rowoff;
-    td.rowoff32 = ctx->d_rowoff32;
-    td.w = ctx->d_w;
-
-    PrepArgs pa;
-    pa.tour = td;
-    pa.N = ctx->N;
-    pa.kind = ctx->kind;
-    pa.xy = ctx->d_xy;
-    pa.dist = ctx->d_dist;
-    pa.ld = ld;
-    pa.stats = ctx->d_stats;
-    pa.ctl = ctx->d_ctl;
-    HIP_TRY(ctx, launch_prep(pa, stream));
-
-    EvalArgs ea;
-    ea.demand = reinterpret_cast<const uint16_t *>(demand);
-    ea.ld = ld;
-    ea.S = S;
-    ea.Q = Q;
-    ea.tour = td;
-    ea.cost = cost;
-    ea.ldc = ldc;
-    ea.stats = ctx->d_stats;
-    ea.ctl = ctx->d_ctl;
-    ea.maxn = maxn;
-
-    int form = ctx->form;
-    if (form == SPLIT_FORM_AUTO) form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
-    // The lane kernel addresses demands with 32-bit buffer offsets.
-    const __int128 lane_bytes = ((__int128)(max_id - 1) * ld + S) * 2;
-    const bool lane_addressable = lane_bytes <= (__int128)kRowAbsent;
-    ea.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
-    if (form == SPLIT_FORM_LANE && !lane_addressable) form = SPLIT_FORM_WAVE;
-    const int64_t items = nsb * T;
-    ea.lane_grid = (int32_t)(items < ctx->lane_grid ? items : ctx->lane_grid);
-    hipEvent_t stop = nullptr;
-    st = timing_begin(ctx, stream, &stop);
-    if (st != SPLIT_OK) return st;
-    if (form == SPLIT_FORM_WAVE) {
-        ctx->tname = wave_kernel_name();
-        HIP_TRY(ctx, launch_wave_all(ea, stream));
-        if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
-    } else {
-        ctx->tname = lane_kernel_name();
-        HIP_TRY(ctx, launch_lane(ea, stream));
-        if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
-        HIP_TRY(ctx, launch_wave_fallback(ea, stream));
-    }
-
-    MomentArgs ma;
-    ma.cost = cost;
-    ma.ldc = ldc;
-    ma.S = S;
-    ma.T = T;
-    ma.partials = ctx->d_partials;
-    ma.nblocks = nblk;
-    ma.stats = ctx->d_stats;
-    HIP_TRY(ctx, launch_moments(ma, stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_stats, ctx->d_stats, sizeof(DevStats) * (size_t)T,
-                                hipMemcpyDeviceToHost, stream));
-    HIP_TRY(ctx, hipEventRecord(ctx->stats_ev, stream));
-    ctx->have_call = true;
-    ctx->last_S = S;
-    ctx->last_T = T;
-    return SPLIT_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const int16_t *demand,
                         int64_t S, int64_t ld, int32_t Q, int32_t *cost, split_stats *stats,
@@ -544,17 +718,7 @@ split_status split_batch_stats_get(split_ctx *ctx, split_stats *stats, int32_t *
     if (!ctx->have_call) return fail(ctx, SPLIT_E_INVAL, "split_batch_stats_get: no evaluation yet");
     DeviceGuard g(ctx->device);
     HIP_TRY(ctx, hipEventSynchronize(ctx->stats_ev));
-    int bad = -1;
-    for (int32_t t = 0; t < ctx->last_T; ++t) {
-        const DevStats &d = ctx->h_stats[t];
-        if (stats) fill_stats(d, ctx->last_S, stats + t);
-        if (tour_status) tour_status[t] = d.err_demand ? SPLIT_E_DEMAND : SPLIT_OK;
-        if (d.err_demand && bad < 0) bad = t;
-    }
-    if (bad >= 0)
-        return fail(ctx, SPLIT_E_DEMAND, "tour %d: a scenario has a demand q < 0 or q > Q on the "
-                    "tour", bad);
-    return SPLIT_OK;
+    return report(ctx, ctx->h_stats, ctx->last_T, ctx->last_S, stats, tour_status);
 }
 
 split_status split_stats_get(split_ctx *ctx, split_stats *stats)
@@ -577,8 +741,133 @@ split_status split_set_form(split_ctx *ctx, int form)
     if (!ctx) return SPLIT_E_INVAL;
     if (form != SPLIT_FORM_AUTO && form != SPLIT_FORM_LANE && form != SPLIT_FORM_WAVE)
         return fail(ctx, SPLIT_E_INVAL, "split_set_form: unknown form %d", form);
-    ctx->form = form;
+    ctx->tuning.form = form;
     return SPLIT_OK;
+}
+
+split_status split_tuning_set(split_ctx *ctx, const split_tuning *tuning)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    if (!tuning) return fail(ctx, SPLIT_E_INVAL, "split_tuning_set: NULL tuning");
+    split_status st = check_tuning(ctx, *tuning);
+    if (st != SPLIT_OK) return st;
+    ctx->tuning = *tuning;
+    return SPLIT_OK;
+}
+
+split_status split_tuning_get(split_ctx *ctx, split_tuning *tuning)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    if (!tuning) return fail(ctx, SPLIT_E_INVAL, "split_tuning_get: NULL tuning");
+    *tuning = ctx->tuning;
+    return SPLIT_OK;
+}
+
+split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t *tour_ptr,
+                            int32_t T, const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                            int32_t *cost, int64_t ldc, int32_t reps, void *hip_stream,
+                            split_tuning *best, double *best_ms)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    if (reps < 1 || reps > 1000)
+        return fail(ctx, SPLIT_E_INVAL, "split_autotune: need 1 <= reps <= 1000");
+    if (ctx->inst.kind < 0) return fail(ctx, SPLIT_E_INVAL, "split_autotune: no instance set");
+    if (!demand || !cost) return fail(ctx, SPLIT_E_INVAL, "split_autotune: NULL pointer");
+    split_status st = check_shape(ctx, "split_autotune", S, ld, Q, ldc);
+    if (st != SPLIT_OK) return st;
+    BatchInfo bi;
+    st = check_tours(ctx, "split_autotune", ctx->inst, ctx->seen, tours, tour_ptr, T, S, &bi);
+    if (st != SPLIT_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
+    hipStream_t stream = (hipStream_t)hip_stream;
+
+    const split_tuning saved = ctx->tuning;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto finish = [&](split_status s) {
+        ctx->timing = saved_timing;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s != SPLIT_OK) ctx->tuning = saved;
+        return s;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return finish(fail(ctx, SPLIT_E_HIP, "split_autotune: hipEventCreate failed"));
+
+    // mean milliseconds of one whole evaluation (upload, kernels, statistics) under tuning c,
+    // on the first s_eval scenarios
+    auto measure = [&](const split_tuning &c, int64_t s_eval, double *ms) -> split_status {
+        ctx->tuning = c;
+        split_status s = eval_batch(ctx, "split_autotune", tours, tour_ptr, T, demand, s_eval, ld,
+                                    Q, cost, ldc, stream);  // warm-up
+        if (s != SPLIT_OK) return s;
+        s = split_batch_stats_get(ctx, nullptr, nullptr);
+        if (s != SPLIT_OK) return s;
+        if (hipEventRecord(e0, stream) != hipSuccess)
+            return fail(ctx, SPLIT_E_HIP, "split_autotune: hipEventRecord failed");
+        for (int r = 0; r < reps; ++r) {
+            s = eval_batch(ctx, "split_autotune", tours, tour_ptr, T, demand, s_eval, ld, Q, cost,
+                           ldc, stream);
+            if (s != SPLIT_OK) return s;
+        }
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(ctx, SPLIT_E_HIP, "split_autotune: timing events failed");
+        float el = 0.f;
+        if (hipEventElapsedTime(&el, e0, e1) != hipSuccess)
+            return fail(ctx, SPLIT_E_HIP, "split_autotune: hipEventElapsedTime failed");
+        *ms = (double)el / reps;
+        return split_batch_stats_get(ctx, nullptr, nullptr);
+    };
+
+    split_tuning win = saved;
+    double win_ms = 1e300;
+    const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0}, S, ld, T,
+                                      bi.maxn, bi.max_id);
+    if (lane_probe.form == SPLIT_FORM_LANE) {
+        const int32_t per_cu[] = {0, 8, 4, 2};
+        for (int32_t pc : per_cu)
+            for (int32_t order = 0; order < 2; ++order) {
+                if (T == 1 && order == 1) continue;  // one tour: the order is moot
+                const split_tuning c = {SPLIT_FORM_LANE, pc, order, 0};
+                double ms = 0.0;
+                st = measure(c, S, &ms);
+                if (st != SPLIT_OK) return finish(st);
+                if (ms < win_ms) {
+                    win_ms = ms;
+                    win = c;
+                }
+            }
+    }
+    // The wave form costs about S times one scenario's evaluation: try it in full only when a
+    // run on at most 256 scenarios, scaled to S, is within 1.5x of the best so far.
+    const int64_t s_probe = S < 256 ? S : 256;
+    double probe_ms = 0.0;
+    st = measure(split_tuning{SPLIT_FORM_WAVE, 0, 0, 0}, s_probe, &probe_ms);
+    if (st != SPLIT_OK) return finish(st);
+    if (probe_ms * ((double)S / (double)s_probe) < 1.5 * win_ms) {
+        const int32_t grids[] = {0, ctx->cus * 8};
+        for (int32_t wg : grids) {
+            const split_tuning c = {SPLIT_FORM_WAVE, 0, 0, wg};
+            double ms = 0.0;
+            st = measure(c, S, &ms);
+            if (st != SPLIT_OK) return finish(st);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = c;
+            }
+        }
+    }
+    // leave the context's latest evaluation the full one under the chosen tuning
+    ctx->tuning = win;
+    st = eval_batch(ctx, "split_autotune", tours, tour_ptr, T, demand, S, ld, Q, cost, ldc, stream);
+    if (st != SPLIT_OK) return finish(st);
+    st = split_batch_stats_get(ctx, nullptr, nullptr);
+    if (st != SPLIT_OK) return finish(st);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return finish(SPLIT_OK);
 }
 
 split_status split_timing_enable(split_ctx *ctx, int enable)
@@ -609,6 +898,178 @@ split_status split_timing_reset(split_ctx *ctx)
     ctx->ms_acc = 0.0;
     ctx->launches = 0;
     return st;
+}
+
+// ------------------------------------------------------------------------- graphs
+
+void split_graph_destroy(split_graph *gr)
+{
+    if (!gr) return;
+    {
+        DeviceGuard g(gr->ctx->device);
+        for (int k = 0; k < kGraphSlots; ++k)
+            if (gr->used[k]) (void)hipEventSynchronize(gr->done[k]);
+        for (int k = 0; k < kGraphSlots; ++k) {
+            if (gr->exec[k]) (void)hipGraphExecDestroy(gr->exec[k]);
+            if (gr->graph[k]) (void)hipGraphDestroy(gr->graph[k]);
+            if (gr->done[k]) (void)hipEventDestroy(gr->done[k]);
+            if (gr->h_stage[k]) (void)hipHostFree(gr->h_stage[k]);
+            if (gr->h_stats[k]) (void)hipHostFree(gr->h_stats[k]);
+        }
+        if (gr->cap_stream) (void)hipStreamDestroy(gr->cap_stream);
+        free_buffers(gr->buf);
+        free_instance(gr->inst);
+    }
+    delete gr;
+}
+
+split_status split_graph_create(split_ctx *ctx, int32_t max_T, int64_t max_total_n,
+                                const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                                int32_t *cost, int64_t ldc, split_graph **out)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    if (!out) return fail(ctx, SPLIT_E_INVAL, "split_graph_create: NULL out");
+    *out = nullptr;
+    if (ctx->inst.kind < 0) return fail(ctx, SPLIT_E_INVAL, "split_graph_create: no instance set");
+    if (!demand || !cost) return fail(ctx, SPLIT_E_INVAL, "split_graph_create: NULL pointer");
+    split_status st = check_shape(ctx, "split_graph_create", S, ld, Q, ldc);
+    if (st != SPLIT_OK) return st;
+    if (max_T < 1 || max_total_n < max_T || max_total_n > (int64_t)max_T * ctx->inst.N)
+        return fail(ctx, SPLIT_E_INVAL, "split_graph_create: need 1 <= max_T <= max_total_n <= "
+                    "max_T * N");
+    if ((__int128)((S + 63) / 64) * max_T >= ((__int128)1 << 31))
+        return fail(ctx, SPLIT_E_INVAL, "split_graph_create: max_T * ceil(S / 64) must be below "
+                    "2^31");
+    const int32_t N = ctx->inst.N;
+    if ((__int128)4 * ((__int128)N + 1) * ctx->inst.max_arc >= ((__int128)1 << 31))
+        return fail(ctx, SPLIT_E_RANGE, "split_graph_create: 4*(N+1)*max_arc exceeds 2^31");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
+
+    split_graph *gr = new (std::nothrow) split_graph();
+    if (!gr) return fail(ctx, SPLIT_E_NOMEM, "split_graph_create: out of host memory");
+    gr->ctx = ctx;
+    bool capturing = false;
+    auto bail = [&](split_status s) {
+        if (capturing) {
+            hipGraph_t dropped = nullptr;
+            (void)hipStreamEndCapture(gr->cap_stream, &dropped);
+            if (dropped) (void)hipGraphDestroy(dropped);
+        }
+        split_graph_destroy(gr);
+        return s;
+    };
+    // the graph's own copy of the instance: later changes to the context's do not reach it
+    gr->inst.N = N;
+    gr->inst.kind = ctx->inst.kind;
+    gr->inst.max_arc = ctx->inst.max_arc;
+    const size_t V = (size_t)N + 1;
+    if (ctx->inst.kind == 0) {
+        if (hipMalloc(&gr->inst.d_xy, sizeof(int32_t) * 2 * V) != hipSuccess ||
+            hipMemcpy(gr->inst.d_xy, ctx->inst.d_xy, sizeof(int32_t) * 2 * V,
+                      hipMemcpyDeviceToDevice) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_NOMEM, "split_graph_create: instance copy failed"));
+    } else {
+        if (hipMalloc(&gr->inst.d_dist, sizeof(int32_t) * V * V) != hipSuccess ||
+            hipMemcpy(gr->inst.d_dist, ctx->inst.d_dist, sizeof(int32_t) * V * V,
+                      hipMemcpyDeviceToDevice) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_NOMEM, "split_graph_create: instance copy failed"));
+    }
+    gr->seen.assign(V, 0);
+    gr->max_T = max_T;
+    gr->max_total_n = max_total_n;
+    gr->S = S;
+    gr->ld = ld;
+    gr->ldc = ldc;
+    gr->Q = Q;
+    gr->order = ctx->tuning.order;
+    gr->layout = stage_layout(max_T, max_total_n);
+    const int32_t nblk = moment_blocks(S);
+    st = ensure_buffers(ctx, gr->buf, max_T, max_total_n, (int64_t)gr->layout.bytes,
+                        (int64_t)nblk * max_T, true);
+    if (st != SPLIT_OK) return bail(st);
+    // any tour of the instance: lengths up to N, ids up to N
+    gr->plan = make_plan(ctx, ctx->tuning, S, ld, max_T, N, N);
+    if (hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        gr->cap_stream = nullptr;
+        return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: hipStreamCreate failed"));
+    }
+    for (int k = 0; k < kGraphSlots; ++k) {
+        if (hipHostMalloc((void **)&gr->h_stage[k], gr->layout.bytes, 0) != hipSuccess ||
+            hipHostMalloc((void **)&gr->h_stats[k], sizeof(DevStats) * (size_t)max_T, 0) !=
+                hipSuccess)
+            return bail(fail(ctx, SPLIT_E_NOMEM, "split_graph_create: pinned allocation failed"));
+        memset(gr->h_stage[k], 0, gr->layout.bytes);
+        if (hipEventCreateWithFlags(&gr->done[k], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: hipEventCreate failed"));
+    }
+    // one graph per host slot: upload of the slot's header, the kernels, the statistics copy
+    for (int k = 0; k < kGraphSlots; ++k) {
+        if (hipStreamBeginCapture(gr->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: hipStreamBeginCapture failed"));
+        capturing = true;
+        if (hipMemcpyAsync(gr->buf.d_stage, gr->h_stage[k], gr->layout.bytes,
+                           hipMemcpyHostToDevice, gr->cap_stream) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: capture of the upload failed"));
+        st = enqueue_kernels(ctx, gr->inst, gr->buf, gr->layout, gr->plan, demand, S, ld, Q, cost,
+                             ldc, gr->cap_stream, false);
+        if (st != SPLIT_OK) return bail(st);
+        if (hipMemcpyAsync(gr->h_stats[k], gr->buf.d_stats, sizeof(DevStats) * (size_t)max_T,
+                           hipMemcpyDeviceToHost, gr->cap_stream) != hipSuccess)
+            return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: capture of the copy failed"));
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(gr->cap_stream, &graph);
+        capturing = false;
+        gr->graph[k] = graph;
+        if (e != hipSuccess || !graph)
+            return bail(hip_fail(ctx, e, "split_graph_create: hipStreamEndCapture"));
+        if (hipGraphInstantiate(&gr->exec[k], graph, nullptr, nullptr, 0) != hipSuccess) {
+            gr->exec[k] = nullptr;
+            return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: hipGraphInstantiate failed"));
+        }
+    }
+    *out = gr;
+    return SPLIT_OK;
+}
+
+split_status split_graph_launch(split_graph *gr, const int32_t *tours, const int64_t *tour_ptr,
+                                int32_t T, void *hip_stream)
+{
+    if (!gr) return SPLIT_E_INVAL;
+    split_ctx *ctx = gr->ctx;
+    if (T > gr->max_T)
+        return fail(ctx, SPLIT_E_INVAL, "split_graph_launch: T = %d exceeds the graph's %d", T,
+                    gr->max_T);
+    BatchInfo bi;
+    split_status st = check_tours(ctx, "split_graph_launch", gr->inst, gr->seen, tours, tour_ptr,
+                                  T, gr->S, &bi);
+    if (st != SPLIT_OK) return st;
+    if (bi.total_n > gr->max_total_n)
+        return fail(ctx, SPLIT_E_INVAL, "split_graph_launch: %lld positions exceed the graph's "
+                    "%lld", (long long)bi.total_n, (long long)gr->max_total_n);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
+    const int k = gr->next;
+    if (gr->used[k]) HIP_TRY(ctx, hipEventSynchronize(gr->done[k]));
+    stage_write(gr->h_stage[k], gr->layout, tours, tour_ptr, T, gr->order);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    HIP_TRY(ctx, hipGraphLaunch(gr->exec[k], stream));
+    HIP_TRY(ctx, hipEventRecord(gr->done[k], stream));
+    gr->used[k] = true;
+    gr->last = k;
+    gr->last_T = T;
+    gr->next = (k + 1) % kGraphSlots;
+    return SPLIT_OK;
+}
+
+split_status split_graph_stats(split_graph *gr, split_stats *stats, int32_t *tour_status)
+{
+    if (!gr) return SPLIT_E_INVAL;
+    split_ctx *ctx = gr->ctx;
+    if (gr->last < 0) return fail(ctx, SPLIT_E_INVAL, "split_graph_stats: no launch yet");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(ctx, hipEventSynchronize(gr->done[gr->last]));
+    return report(ctx, gr->h_stats[gr->last], gr->last_T, gr->S, stats, tour_status);
 }
 
 }  // extern "C"

@@ -5,6 +5,9 @@
 // (split_eval is the batch of one). Per-tour arrays are concatenated: tour t's positions are
 // tours[tptr[t] .. tptr[t+1]) and its derived arrays start at abase(t) = tptr[t] + t * (1 +
 // kRowPad), each holding n_t + 1 + kRowPad entries.
+//
+// The kernels read T from device memory (the staged header), and their grids are sized for an
+// upper bound of T: one captured HIP graph then serves every batch up to its capacity.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,11 +57,15 @@ __host__ __device__ inline int64_t tour_abase(const int64_t *tptr, int t)
     return tptr[t] + (int64_t)t * (1 + kRowPad);
 }
 
+// Staged header, uploaded before every evaluation: int64 T, int64 tptr[T + 1], int32 order[T]
+// (the lane kernel's work order), int32 tours[tptr[T]], each part at an offset fixed by the
+// capacity the buffers were laid out for.
 struct TourDev {
+    const int64_t *nt;     // [1] number of tours T of this evaluation
     const int32_t *tours;  // [tptr[T]] concatenated tours
     const int64_t *tptr;   // [T + 1]
-    const int32_t *order;  // [T] tours by decreasing length (the lane kernel's work order)
-    int32_t T;
+    const int32_t *order;  // [T] work order of the lane kernel
+    int32_t T_grid;        // upper bound of T that the launch grids are sized for
     int64_t *rowoff;       // concatenated, see above
     uint32_t *rowoff32;    // rowoff mod 2^32 (exact where it is used), kRowAbsent where absent
     int32_t *w;
@@ -86,15 +93,17 @@ struct EvalArgs {
     DevStats *stats;         // [T]
     BatchCtl *ctl;
     uint32_t lane_bytes;     // lane kernel: bytes of demand it may address, <= kRowAbsent
-    int32_t lane_grid;       // lane kernel: persistent workgroups
-    int32_t maxn;            // longest tour of the batch (sizes the wave kernel's LDS)
+    int32_t lane_grid;       // lane kernel workgroups (>= the work items: one item each)
+    int32_t wave_grid;       // wave kernel workgroups of a full evaluation (form wave)
+    int32_t maxn;            // bound on the tour lengths (sizes the wave kernel's LDS)
 };
 
 struct MomentArgs {
     const int32_t *cost;           // [T][ldc]
     int64_t ldc;
     int64_t S;
-    int32_t T;
+    const int64_t *nt;             // [1] T
+    int32_t T_grid;
     unsigned long long *partials;  // [T][nblocks][3]
     int32_t nblocks;               // per tour
     DevStats *stats;               // [T]

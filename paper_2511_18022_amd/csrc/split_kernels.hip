@@ -47,12 +47,14 @@ __device__ __forceinline__ int32_t arc_cost(const PrepArgs &a, int u, int v)
 }
 
 // One workgroup per tour: the weights w, the row offsets and the padding of tour t, and the
-// zeroed result block of the tour. Workgroup 0 also resets the batch counters.
+// zeroed result block of the tour. Workgroup 0 also resets the batch counters. Workgroups
+// past the call's T return at once.
 __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 {
     __shared__ long long red[1024];
     const int tid = threadIdx.x;
     const int t = blockIdx.x;
+    if (t >= *a.tour.nt) return;
     const int32_t *tour = a.tour.tours + a.tour.tptr[t];
     const int n = (int)(a.tour.tptr[t + 1] - a.tour.tptr[t]);
     const int64_t ab = tour_abase(a.tour.tptr, t);
@@ -606,9 +608,10 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
     }
 }
 
-// Persistent: each workgroup takes (tour, scenario block) items from a queue in the order of
-// decreasing tour length until the queue is empty. The next item's index is fetched while the
-// current one runs.
+// Work item k = (tour order[k / nsb], scenario block k % nsb), nsb = ceil(S / 64). Workgroup b
+// runs item b, then takes items gridDim.x, gridDim.x + 1, ... from a queue until none is left
+// (a grid of at least T * nsb workgroups runs one item each and never touches the queue). The
+// next item's index is fetched while the current one runs.
 __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
 {
     __shared__ LaneLds L;
@@ -618,13 +621,14 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.demand, (short)0, (int)a.lane_bytes, 0x00020000);
     const long long nsb = (a.S + 63) / 64;
-    const long long items = nsb * a.tour.T;
-    uint32_t k = 0;
-    if (lane == 0) k = atomicAdd(&a.ctl->head, 1u);
-    k = __builtin_amdgcn_readfirstlane(k);
+    const long long items = nsb * *(ci64 *)a.tour.nt;
+    const bool queue = (long long)gridDim.x < items;
+    uint32_t k = blockIdx.x;
     while ((long long)k < items) {
-        uint32_t knext = 0;
-        if (lane == 0) knext = atomicAdd(&a.ctl->head, 1u);
+        uint32_t knext = 0xFFFFFFFFu;
+        if (queue) {
+            if (lane == 0) knext = gridDim.x + atomicAdd(&a.ctl->head, 1u);
+        }
         const long long r = (long long)k / nsb;
         const int t = ((ci32 *)a.tour.order)[r];
         lane_item(L, a, t, (long long)k - r * nsb, rsrc);
@@ -722,7 +726,7 @@ __global__ __launch_bounds__(64) void split_wave_kernel(EvalArgs a, int mode)
     extern __shared__ int32_t lds[];
     int32_t *G = lds;
     int32_t *PP = lds + (a.maxn + 1);
-    const long long T = a.tour.T;
+    const long long T = *a.tour.nt;
     if (mode == 0) {
         for (long long k = blockIdx.x; k < T * a.S; k += gridDim.x) {
             const int t = (int)(k / a.S);
@@ -780,10 +784,11 @@ __device__ void block_reduce3(unsigned long long &s, unsigned long long &lo,
     hi = rh[0];
 }
 
-// grid (nblocks, T): workgroup (b, t) sums a strided share of tour t's costs
+// grid (nblocks, T_grid): workgroup (b, t) sums a strided share of tour t's costs
 __global__ __launch_bounds__(256) void split_moments_partial(MomentArgs a)
 {
     const int t = blockIdx.y;
+    if (t >= *a.nt) return;
     const int32_t *cost = a.cost + (long long)t * a.ldc;
     unsigned long long s = 0, lo = 0, hi = 0;
     for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < a.S;
@@ -801,10 +806,11 @@ __global__ __launch_bounds__(256) void split_moments_partial(MomentArgs a)
     }
 }
 
-// grid T: workgroup t combines the partials of tour t
+// grid T_grid: workgroup t combines the partials of tour t
 __global__ __launch_bounds__(256) void split_moments_final(MomentArgs a)
 {
     const int t = blockIdx.x;
+    if (t >= *a.nt) return;
     const unsigned long long *p = a.partials + 3 * (long long)t * a.nblocks;
     unsigned long long s = 0, lo = 0, hi = 0;
     for (int b = threadIdx.x; b < a.nblocks; b += 256) {
@@ -823,7 +829,7 @@ __global__ __launch_bounds__(256) void split_moments_final(MomentArgs a)
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(split_prep_kernel, dim3(a.tour.T), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(split_prep_kernel, dim3(a.tour.T_grid), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -847,8 +853,8 @@ hipError_t launch_wave_all(const EvalArgs &a, hipStream_t stream)
 {
     hipError_t e = wave_lds_allow(wave_lds_bytes(a.maxn));
     if (e != hipSuccess) return e;
-    const long long work = a.S * a.tour.T;
-    const long long nb = work < 65536 ? work : 65536;
+    const long long work = a.S * a.tour.T_grid;
+    const long long nb = work < a.wave_grid ? work : a.wave_grid;
     hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.maxn), stream,
                        a, 0);
     return hipGetLastError();
@@ -858,7 +864,7 @@ hipError_t launch_wave_fallback(const EvalArgs &a, hipStream_t stream)
 {
     hipError_t e = wave_lds_allow(wave_lds_bytes(a.maxn));
     if (e != hipSuccess) return e;
-    const long long work = (a.S + 63) / 64 * a.tour.T;
+    const long long work = (a.S + 63) / 64 * a.tour.T_grid;
     const long long nb = work < 2048 ? work : 2048;
     hipLaunchKernelGGL(split_wave_kernel, dim3((unsigned)nb), dim3(64), wave_lds_bytes(a.maxn), stream,
                        a, 1);
@@ -875,10 +881,10 @@ int32_t moment_blocks(int64_t S)
 
 hipError_t launch_moments(const MomentArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(split_moments_partial, dim3(a.nblocks, a.T), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(split_moments_partial, dim3(a.nblocks, a.T_grid), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(split_moments_final, dim3(a.T), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(split_moments_final, dim3(a.T_grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -46,6 +46,21 @@ def test_null_context_is_rejected_without_touching_the_gpu(lib):
     assert lib.split_ctx_create(0, None) == sg.SPLIT_E_INVAL
     assert lib.split_last_error(null) == b"null context"
     lib.split_ctx_destroy(null)
+    assert lib.split_tuning_set(null, None) == sg.SPLIT_E_INVAL
+    assert lib.split_tuning_get(null, None) == sg.SPLIT_E_INVAL
+    assert lib.split_autotune(null, None, None, 1, None, 1, 1, 1, None, 1, 1, None, None,
+                              None) == sg.SPLIT_E_INVAL
+    assert lib.split_graph_create(null, 1, 1, None, 1, 1, 1, None, 1, None) == sg.SPLIT_E_INVAL
+    assert lib.split_graph_launch(null, None, None, 1, None) == sg.SPLIT_E_INVAL
+    assert lib.split_graph_stats(null, None, None) == sg.SPLIT_E_INVAL
+    lib.split_graph_destroy(null)
+
+
+def test_tuning_struct_matches_header():
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^}]*)\} split_tuning;", text).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == [f for f, _ in sg.SplitTuningC._fields_]
 
 
 def test_status_codes_match_header():
