@@ -126,13 +126,14 @@ def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
                       "ms_per_copy": el * 1e3, "GBps_read_plus_write": 2 * nbytes / el / 1e9}))
 
 
-def timed_steps(ctx, step, steps: int, warmup: int):
-    """Warm-up steps, then `steps` timed steps between device synchronizations. Returns
-    (ms per step, dominant-kernel average ms, kernel name)."""
+def timed_steps(ctx, step, wait, steps: int, warmup: int):
+    """Warm-up steps, then `steps` timed steps between device synchronizations, with the
+    dominant kernel of eager evaluations timed by HIP events on their stream. Returns
+    (ms per step, dominant-kernel average ms, kernel name, timed launches)."""
     import torch
     for _ in range(warmup):
         step()
-    ctx.batch_stats()
+    wait()
     torch.cuda.synchronize()
     ctx.timing(True)
     ctx.timing_reset()
@@ -140,7 +141,7 @@ def timed_steps(ctx, step, steps: int, warmup: int):
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-    ctx.batch_stats()
+    wait()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kern_ms, launches, kname = ctx.timing_get()
@@ -157,6 +158,13 @@ def main():
     ap.add_argument("--workload", default="copula-n1000")
     ap.add_argument("--form", default="auto", choices=["auto", "lane", "wave"])
     ap.add_argument("--tours", type=int, default=None, help="batch workloads: number of tours")
+    ap.add_argument("--launch", default=None, choices=["eager", "graph"],
+                    help="time eager calls or replays of a captured graph (default: graph for "
+                         "batch workloads, eager otherwise)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch workloads: keep the default launch choices")
+    ap.add_argument("--tuning", default=None, metavar="PER_CU,ORDER",
+                    help="lane form with these launch choices instead of autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alu-count", action="store_true",
                     help="skip counting the window work that sizes the ALU roofline")
@@ -206,8 +214,21 @@ def main():
     h2d_s = time.perf_counter() - t0
     log(f"uploaded {dem.numel() * 2 / 1e9:.3f} GB in {h2d_s:.3f}s")
 
+    launch = args.launch or ("graph" if batch else "eager")
+    tuning, tune_ms = None, None
     if batch:
         cost = torch.empty((T, w.S), dtype=torch.int32, device="cuda")
+        if args.tuning:
+            pc, order = (int(x) for x in args.tuning.split(","))
+            ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, pc, order, 0))
+            tuning = {"form": sg.FORM_LANE, "lane_per_cu": pc, "order": order, "wave_grid": 0}
+        elif not args.no_autotune:
+            t0 = time.perf_counter()
+            tu, tune_ms, _ = ctx.autotune(tours, dem, w.Q, reps=3)
+            tuning = {"form": tu.form, "lane_per_cu": tu.lane_per_cu, "order": tu.order,
+                      "wave_grid": tu.wave_grid}
+            log(f"autotune: {tu} {tune_ms:.4f} ms per evaluation "
+                f"({time.perf_counter() - t0:.1f}s)")
 
         def step():
             ctx.eval_batch(tours, dem, w.Q, cost=cost, sync=False)
@@ -217,8 +238,20 @@ def main():
         def step():
             ctx.eval(w.tour, dem, w.Q, cost=cost, sync=False)
 
-    ms_step, kern_avg_ms, kname, launches = timed_steps(ctx, step, args.steps, args.warmup)
+    # eager evaluations: the dominant kernel's duration for the roofline
+    ms_eager, kern_avg_ms, kname, launches = timed_steps(ctx, step, ctx.batch_stats, args.steps,
+                                                         args.warmup)
     stats, status = ctx.batch_stats()
+    ms_step = ms_eager
+    if launch == "graph":
+        g = ctx.graph(T, sum(len(t) for t in tours), dem, w.Q,
+                      cost=cost if batch else cost.view(1, -1))
+        ms_step, _, _, _ = timed_steps(ctx, lambda: g.launch(tours), g.stats, args.steps,
+                                       args.warmup)
+        gstats, gstatus = g.stats()
+        assert [s.sum for s in gstats] == [s.sum for s in stats] and gstatus == status
+        g.close()
+        log(f"graph replays: {ms_step:.4f} ms/step (eager {ms_eager:.4f})")
     n_fallback = sum(s.n_fallback for s in stats)
     log(f"{args.steps} steps: {ms_step:.4f} ms/step, {kname} avg {kern_avg_ms:.4f} ms "
         f"({launches} launches), fallback scenarios {n_fallback}, bad tours "
@@ -245,7 +278,11 @@ def main():
     config = {"workload": w.name, "S": w.S, "Q": w.Q, "seed": w.seed, "demand": COPULA_DESC,
               "coords": "integer uniform 1000x1000, rounded Euclidean int32 costs",
               "kernel": kname, "form": args.form, "fallback_scenarios": n_fallback,
+              "launch": launch, "eager_ms_per_step": ms_eager,
               "h2d_GBps": dem.numel() * 2 / h2d_s / 1e9}
+    if tuning is not None:
+        config["tuning"] = tuning
+        config["autotune_ms"] = tune_ms
     if batch:
         config.update({"N": w.N, "tours": T, "n_min": min(len(t) for t in tours),
                        "n_max": max(len(t) for t in tours), "n_sum": sum_n})
@@ -254,6 +291,8 @@ def main():
         roof = dict(alu) if alu else None
         if roof is not None:
             roof["hbm_equivalent"] = hbm
+            # bytes the kernel fetched from the memory fabric (HBM or the last-level cache)
+            roof["traffic"] = measured_traffic(w.name, w.S)
     else:
         config["n"] = w.n
         roof = dict(hbm)
