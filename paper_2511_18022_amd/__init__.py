@@ -28,7 +28,14 @@ EXPORTED = [
     "split_batch_stats_get", "split_set_form", "split_timing_enable", "split_timing_get",
     "split_timing_reset", "split_tuning_set", "split_tuning_get", "split_autotune",
     "split_graph_create", "split_graph_launch", "split_graph_stats", "split_graph_destroy",
+    # include/split_nn.h
+    "split_nn_create", "split_nn_destroy", "split_nn_params_get", "split_nn_params_set",
+    "split_nn_set_norm", "split_nn_set_scenarios", "split_nn_predict", "split_nn_gradient",
+    "split_nn_train_step", "split_nn_train", "split_nn_step", "split_nn_save", "split_nn_load",
+    "split_topk_smallest", "split_nn_screen",
 ]
+NN_PARAMS = 283393
+VOID_FUNCS = ("split_ctx_destroy", "split_last_error", "split_graph_destroy", "split_nn_destroy")
 
 
 class SplitError(RuntimeError):
@@ -113,9 +120,27 @@ def load_library(path: str = LIB_PATH):
     lib.split_graph_stats.argtypes = [P, P, P]
     lib.split_graph_destroy.argtypes = [P]
     lib.split_graph_destroy.restype = None
+    u64, f32, f64 = ctypes.c_uint64, ctypes.c_float, ctypes.c_double
+    lib.split_nn_create.argtypes = [P, u64, f64, ctypes.POINTER(P)]
+    lib.split_nn_destroy.argtypes = [P]
+    lib.split_nn_destroy.restype = None
+    lib.split_nn_params_get.argtypes = [P, P]
+    lib.split_nn_params_set.argtypes = [P, P]
+    lib.split_nn_set_norm.argtypes = [P, f64, f64]
+    lib.split_nn_set_scenarios.argtypes = [P, P, i64, i64, i32]
+    lib.split_nn_predict.argtypes = [P, P, i32, i32, P, P]
+    lib.split_nn_gradient.argtypes = [P, P, P, i32, i32, P, ctypes.POINTER(f64), P]
+    lib.split_nn_train_step.argtypes = [P, P, P, i32, i32, f32, ctypes.POINTER(f64), P]
+    lib.split_nn_train.argtypes = [P, P, P, i64, i32, i32, i64, f32, u64, ctypes.POINTER(f64), P]
+    lib.split_nn_step.argtypes = [P, ctypes.POINTER(i64)]
+    lib.split_nn_save.argtypes = [P, ctypes.c_char_p]
+    lib.split_nn_load.argtypes = [P, ctypes.c_char_p]
+    lib.split_topk_smallest.argtypes = [P, P, i64, i64, P, P]
+    lib.split_nn_screen.argtypes = [P, P, i64, i32, i64, P, i64, i64, i32, P, P, P,
+                                    ctypes.POINTER(i64), ctypes.POINTER(f64), P]
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("split_ctx_destroy", "split_last_error", "split_graph_destroy"):
+        if name not in VOID_FUNCS:
             fn.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -417,3 +442,172 @@ class SplitGraph:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _cuda_i32_matrix(tours):
+    import torch
+    if not (isinstance(tours, torch.Tensor) and tours.is_cuda and tours.dtype == torch.int32 and
+            tours.dim() == 2 and tours.is_contiguous()):
+        raise ValueError("tours must be a contiguous CUDA int32 tensor [T, n]")
+    return tours.shape[0], tours.shape[1]
+
+
+def _cuda_f32_vector(x, T, what):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and
+            x.is_contiguous() and x.numel() >= T):
+        raise ValueError(f"{what} must be a contiguous CUDA float32 tensor with >= {T} values")
+
+
+class SplitNN:
+    """The tour-encoder surrogate (include/split_nn.h) on a SplitContext's device and instance.
+    Tours are CUDA int32 tensors [T, n]; labels are expected costs (CUDA float32 [T])."""
+
+    def __init__(self, ctx: SplitContext, seed: int = 0, length_scale: float = 1000.0):
+        self._ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        ctx._check(self._lib.split_nn_create(ctx._h, int(seed), float(length_scale),
+                                             ctypes.byref(h)))
+        self._h = h
+
+    def _check(self, st):
+        self._ctx._check(st)
+
+    @staticmethod
+    def _stream(stream, device):
+        import torch
+        s = torch.cuda.current_stream(device) if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def params(self):
+        np = _np()
+        out = np.zeros(NN_PARAMS, dtype=np.float32)
+        self._check(self._lib.split_nn_params_get(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        np = _np()
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != NN_PARAMS:
+            raise ValueError(f"need {NN_PARAMS} parameters")
+        self._check(self._lib.split_nn_params_set(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_norm(self, shift: float, scale: float):
+        self._check(self._lib.split_nn_set_norm(self._h, float(shift), float(scale)))
+
+    def set_scenarios(self, demand, Q: int, S: int | None = None):
+        ld, S = _demand_shape(demand, S, None, self._ctx.N)
+        if demand.shape[0] < self._ctx.N:
+            raise ValueError("the demand tensor needs a row for every customer 1..N")
+        self._check(self._lib.split_nn_set_scenarios(self._h, ctypes.c_void_p(demand.data_ptr()),
+                                                     S, ld, int(Q)))
+
+    def predict(self, tours, out=None, stream=None):
+        import torch
+        T, n = _cuda_i32_matrix(tours)
+        if out is None:
+            out = torch.empty(T, dtype=torch.float32, device=tours.device)
+        _cuda_f32_vector(out, T, "out")
+        self._check(self._lib.split_nn_predict(self._h, ctypes.c_void_p(tours.data_ptr()), T, n,
+                                               ctypes.c_void_p(out.data_ptr()),
+                                               self._stream(stream, tours.device)))
+        return out
+
+    def gradient(self, tours, labels, stream=None):
+        np = _np()
+        T, n = _cuda_i32_matrix(tours)
+        _cuda_f32_vector(labels, T, "labels")
+        g = np.zeros(NN_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self._lib.split_nn_gradient(
+            self._h, ctypes.c_void_p(tours.data_ptr()), ctypes.c_void_p(labels.data_ptr()), T, n,
+            g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+            self._stream(stream, tours.device)))
+        return g, float(loss.value)
+
+    def train_step(self, tours, labels, lr: float, stream=None) -> float:
+        T, n = _cuda_i32_matrix(tours)
+        _cuda_f32_vector(labels, T, "labels")
+        loss = ctypes.c_double()
+        self._check(self._lib.split_nn_train_step(
+            self._h, ctypes.c_void_p(tours.data_ptr()), ctypes.c_void_p(labels.data_ptr()), T, n,
+            float(lr), ctypes.byref(loss), self._stream(stream, tours.device)))
+        return float(loss.value)
+
+    def train(self, tours, labels, batch: int, steps: int, lr: float, seed: int = 0,
+              stream=None) -> float:
+        """`steps` Adam steps over the training set; returns the mean batch loss."""
+        count, n = _cuda_i32_matrix(tours)
+        _cuda_f32_vector(labels, count, "labels")
+        loss = ctypes.c_double()
+        self._check(self._lib.split_nn_train(
+            self._h, ctypes.c_void_p(tours.data_ptr()), ctypes.c_void_p(labels.data_ptr()), count,
+            n, int(batch), int(steps), float(lr), int(seed), ctypes.byref(loss),
+            self._stream(stream, tours.device)))
+        return float(loss.value)
+
+    @property
+    def step(self) -> int:
+        s = ctypes.c_int64()
+        self._check(self._lib.split_nn_step(self._h, ctypes.byref(s)))
+        return int(s.value)
+
+    def save(self, path: str):
+        self._check(self._lib.split_nn_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        self._check(self._lib.split_nn_load(self._h, os.fsencode(path)))
+
+    def screen(self, cands, K: int, demand, Q: int, S: int | None = None, pred=None,
+               stream=None):
+        """Predict every candidate, evaluate the K best predictions exactly, return a dict with
+        best_idx, best_mean, short_idx [K], short_mean [K] and pred [C]."""
+        import torch
+        np = _np()
+        C, n = _cuda_i32_matrix(cands)
+        ld, S = _demand_shape(demand, S, None, self._ctx.N)
+        if pred is None:
+            pred = torch.empty(C, dtype=torch.float32, device=cands.device)
+        _cuda_f32_vector(pred, C, "pred")
+        sidx = np.zeros(K, dtype=np.int32)
+        smean = np.zeros(K, dtype=np.float64)
+        bi, bm = ctypes.c_int64(), ctypes.c_double()
+        self._check(self._lib.split_nn_screen(
+            self._h, ctypes.c_void_p(cands.data_ptr()), C, n, int(K),
+            ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q), ctypes.c_void_p(pred.data_ptr()),
+            sidx.ctypes.data_as(ctypes.c_void_p), smean.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(bi), ctypes.byref(bm), self._stream(stream, cands.device)))
+        return {"best_idx": int(bi.value), "best_mean": float(bm.value), "short_idx": sidx,
+                "short_mean": smean, "pred": pred}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.split_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def topk_smallest(ctx: SplitContext, scores, K: int, stream=None):
+    """Indices (CUDA int32 [K], increasing) of the K smallest scores (CUDA float32 [C]); ties at
+    the threshold go to the lower indices."""
+    import torch
+    C = scores.numel()
+    _cuda_f32_vector(scores, C, "scores")
+    idx = torch.empty(int(K), dtype=torch.int32, device=scores.device)
+    s = torch.cuda.current_stream(scores.device) if stream is None else stream
+    ctx._check(ctx._lib.split_topk_smallest(ctx._h, ctypes.c_void_p(scores.data_ptr()), C,
+                                            int(K), ctypes.c_void_p(idx.data_ptr()),
+                                            ctypes.c_void_p(s.cuda_stream)))
+    return idx

@@ -1,0 +1,753 @@
+// HIP kernels of the tour-encoder surrogate on gfx950: features along the tour, four 5-tap
+// conv layers of width 128 as implicit GEMMs on bf16 MFMA (fp32 accumulation), mean-pool and
+// MLP head, the backward pass, Adam, and a top-k selection for screening.
+//
+// Layout: activations are bf16 [T][n + 4][C] (position-major, channels fastest) with two zero
+// rows before and after every tour. The 5-tap window of output position j is then the
+// contiguous span of 5 * C values starting at padded row j, so the conv is a GEMM whose A rows
+// overlap in memory (no im2col copy): out[j][co] = sum_kk X[(row j) * C + kk] * Wf[co][kk],
+// kk = tap * C + ci. The backward-data conv is the same GEMM with the flipped, transposed
+// weights Wb[ci][tap' * 128 + co] = W[4 - tap'][ci][co].
+//
+// MFMA v_mfma_f32_16x16x32_bf16 (checked on the device): lane l holds A[row l % 16][k (l/16)*8
+// + e], B[k (l/16)*8 + e][col l % 16], and D[row (l/16)*4 + i][col l % 16], e < 8, i < 4.
+//
+// Every reduction runs in a fixed order, so results are bitwise reproducible run to run.
+#include "nn_internal.h"
+
+namespace splitgpu {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// fp32 -> bf16 bits, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_bits_f32(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// fp64 -> bf16 bits, round to nearest, ties to even, directly from the double (no fp32 step)
+__device__ __forceinline__ uint16_t bf16_bits_f64(double x)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned long long sign = u >> 63;
+    u &= 0x7FFFFFFFFFFFFFFFull;
+    if (u == 0) return (uint16_t)(sign << 15);
+    // keep 7 fraction bits of the 52: round at bit 45
+    const unsigned long long lsb = (u >> 45) & 1ull;
+    u += 0xFFFFFFFFFFFull + lsb;  // half a unit (2^44) - 1 + lsb
+    const int e = (int)(u >> 52) - 1023;  // unbiased exponent after rounding
+    const uint32_t frac = (uint32_t)((u >> 45) & 0x7Fu);
+    // the values here are normal and well inside the bf16 range
+    const uint32_t be = (uint32_t)(e + 127);
+    return (uint16_t)((sign << 15) | (be << 7) | frac);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ------------------------------------------------------------------------- demand statistics
+
+// One workgroup per customer: exact integer sums of q and q^2 over the S scenarios, then the
+// mean and population standard deviation in double.
+__global__ __launch_bounds__(256) void nn_dstats_kernel(const int16_t *demand, int64_t ld,
+                                                        int64_t S, double *musd)
+{
+    __shared__ long long s1[256], s2[256];
+    const int c = blockIdx.x;
+    const int16_t *row = demand + (long long)c * ld;
+    long long a = 0, b = 0;
+    for (long long s = threadIdx.x; s < S; s += 256) {
+        const long long q = row[s];
+        a += q;
+        b += q * q;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s1[threadIdx.x] += s1[threadIdx.x + off];
+            s2[threadIdx.x] += s2[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = (double)s1[0] / (double)S;
+        const double m2 = (double)s2[0] / (double)S;
+        const double var = m2 - mu * mu;
+        musd[2 * c] = mu;
+        musd[2 * c + 1] = sqrt(var > 0.0 ? var : 0.0);
+    }
+}
+
+// ------------------------------------------------------------------------- features
+
+__device__ __forceinline__ long long nn_dist(const NnInstance &in, int u, int v)
+{
+    if (in.kind == 1) return in.dist[(long long)u * (in.N + 1) + v];
+    const long long dx = (long long)in.xy[2 * u] - in.xy[2 * v];
+    const long long dy = (long long)in.xy[2 * u + 1] - in.xy[2 * v + 1];
+    const long long m = dx * dx + dy * dy;
+    long long k = (long long)sqrt((double)m);
+    while (k * k > m) --k;
+    while ((k + 1) * (k + 1) <= m) ++k;
+    return m - k * k > k ? k + 1 : k;
+}
+
+// One thread per (tour, position): the 8 features in double, rounded once to bf16, written
+// with the 24 zero channels as 64 contiguous bytes. Out-of-range ids set *err and read id 1.
+__global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const int32_t *tours,
+                                                          int32_t T, int32_t n,
+                                                          const double *musd, int32_t Q, double L,
+                                                          uint16_t *X, int32_t *err)
+{
+    const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (m >= (long long)T * n) return;
+    const int t = (int)(m / n), j = (int)(m - (long long)t * n);
+    const int32_t *tour = tours + (long long)t * n;
+    auto id = [&](int k) {
+        int c = tour[k];
+        if (c < 1 || c > in.N) {
+            atomicOr(err, 1);
+            c = 1;
+        }
+        return c;
+    };
+    const int c = id(j);
+    const int prev = j > 0 ? id(j - 1) : 0;
+    const int nxt = j + 1 < n ? id(j + 1) : 0;
+    double f[8];
+    if (in.kind == 0) {
+        f[0] = ((double)in.xy[2 * c] - (double)in.xy[0]) / L;
+        f[1] = ((double)in.xy[2 * c + 1] - (double)in.xy[1]) / L;
+    } else {
+        f[0] = 0.0;
+        f[1] = 0.0;
+    }
+    f[2] = musd[2 * (c - 1)] / (double)Q;
+    f[3] = musd[2 * (c - 1) + 1] / (double)Q;
+    f[4] = (double)nn_dist(in, prev, c) / L;
+    f[5] = (double)nn_dist(in, c, nxt) / L;
+    f[6] = (double)nn_dist(in, 0, c) / L;
+    f[7] = 1.0;
+    u16x8 v;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = bf16_bits_f64(f[k]);
+    u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    u16x8 *dst = reinterpret_cast<u16x8 *>(X + ((long long)t * (n + 4) + j + 2) * kNnCi0);
+    dst[0] = v;
+    dst[1] = zero;
+    dst[2] = zero;
+    dst[3] = zero;
+}
+
+// ------------------------------------------------------------------------- conv (MFMA)
+
+// Y[t][j + 2][co] for M = T * n positions. A workgroup is 4 wavefronts; each wavefront computes
+// 64 positions x 128 channels: 4 x 8 tiles of 16 x 16, K = 5 * CI in steps of 32.
+// MODE 0: Y = bf16(relu(acc + bias[co]))       (forward)
+// MODE 1: Y = bf16(acc) where mask > 0, else 0 (backward data: mask = the layer's input H)
+template <int CI, int MODE>
+__global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const uint16_t *Wt,
+                                                      const float *bias, const uint16_t *mask,
+                                                      uint16_t *Y, int32_t T, int32_t n)
+{
+    constexpr int K = kNnTaps * CI;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long M = (long long)T * n;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 64;
+    if (m0 >= M) return;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    // A row starts (padded row j of tour t, tap 0) of this lane's 4 positions
+    const bf16x8 *arow[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        long long m = m0 + mt * 16 + r16;
+        if (m >= M) m = M - 1;  // the ragged tail reads a valid row; its result is not stored
+        const long long t = m / n, j = m - t * n;
+        arow[mt] = reinterpret_cast<const bf16x8 *>(X + (t * (n + 4) + j) * CI + kq);
+    }
+    const bf16x8 *brow = reinterpret_cast<const bf16x8 *>(Wt + (long long)r16 * K + kq);
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < K / 32; ++kb) {
+        bf16x8 a[4], b[8];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = arow[mt][kb * 4];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) b[nt] = brow[(nt * 16 * K) / 8 + kb * 4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 8; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt],
+                                                                      0, 0, 0);
+    }
+    // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long long m = m0 + mt * 16 + (lane >> 4) * 4 + i;
+            if (m >= M) continue;
+            const long long t = m / n, j = m - t * n;
+            const long long base = (t * (n + 4) + j + 2) * kNnWidth;
+#pragma unroll
+            for (int nt = 0; nt < 8; ++nt) {
+                const int co = nt * 16 + r16;
+                float v = acc[mt][nt][i];
+                if (MODE == 0) {
+                    v += bias[co];
+                    v = v > 0.f ? v : 0.f;
+                } else {
+                    if (mask[base + co] == 0 || (mask[base + co] & 0x8000u)) v = 0.f;
+                }
+                Y[base + co] = bf16_bits_f32(v);
+            }
+        }
+}
+
+// ------------------------------------------------------------------------- pool and head
+
+// One workgroup of 128 threads per tour: z = mean over positions of H4, a = Wa z + ba,
+// u = relu(a), y = wb . u + bb (fixed-order tree), pred = y * scale + shift.
+__global__ __launch_bounds__(128) void nn_head_fwd_kernel(const uint16_t *H4, int32_t T,
+                                                          int32_t n, const float *P, float *z,
+                                                          float *a, float *y, float *pred,
+                                                          double shift, double scale)
+{
+    __shared__ float zs[kNnWidth];
+    __shared__ float red[kNnWidth];
+    const int t = blockIdx.x, c = threadIdx.x;
+    const uint16_t *h = H4 + ((long long)t * (n + 4) + 2) * kNnWidth + c;
+    float s = 0.f;
+    for (int j = 0; j < n; ++j) s += bf16_to_f32(h[(long long)j * kNnWidth]);
+    const float zc = s / (float)n;
+    zs[c] = zc;
+    z[(long long)t * kNnWidth + c] = zc;
+    __syncthreads();
+    const float *Wa = P + kNnOffWa;
+    float acc = P[kNnOffBa + c];
+    for (int i = 0; i < kNnWidth; ++i) acc += Wa[c * kNnWidth + i] * zs[i];
+    a[(long long)t * kNnWidth + c] = acc;
+    red[c] = P[kNnOffWb + c] * (acc > 0.f ? acc : 0.f);
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if (c < off) red[c] += red[c + off];
+        __syncthreads();
+    }
+    if (c == 0) {
+        const float yt = red[0] + P[kNnOffBb];
+        y[t] = yt;
+        if (pred) pred[t] = (float)((double)yt * scale + shift);
+    }
+}
+
+// Loss and head backward of a batch: dy_t = 2 (y_t - yhat_t) / T with yhat = (label - shift) /
+// scale; da = dy wb [a > 0]; dz = Wa^T da. One workgroup per tour; loss terms per tour.
+__global__ __launch_bounds__(128) void nn_head_bwd_kernel(const float *labels, int32_t T,
+                                                          const float *P, const float *a,
+                                                          const float *y, double shift,
+                                                          double scale, float *da, float *dz,
+                                                          float *dy, float *loss_terms)
+{
+    __shared__ float das[kNnWidth];
+    const int t = blockIdx.x, c = threadIdx.x;
+    const float yhat = (float)(((double)labels[t] - shift) / scale);
+    const float err = y[t] - yhat;
+    const float d = 2.f * err / (float)T;
+    const float at = a[(long long)t * kNnWidth + c];
+    const float dac = at > 0.f ? d * P[kNnOffWb + c] : 0.f;
+    das[c] = dac;
+    da[(long long)t * kNnWidth + c] = dac;
+    if (c == 0) {
+        dy[t] = d;
+        loss_terms[t] = err * err;
+    }
+    __syncthreads();
+    const float *Wa = P + kNnOffWa;
+    float s = 0.f;
+    for (int o = 0; o < kNnWidth; ++o) s += Wa[o * kNnWidth + c] * das[o];
+    dz[(long long)t * kNnWidth + c] = s;
+}
+
+// Head parameter gradients, summed over the batch in tour order. Grid kNnWidth + 1 workgroups of
+// 128: workgroup o < 128 writes gWa[o][*] and gba[o]; the last writes gwb and gbb.
+__global__ __launch_bounds__(128) void nn_head_grad_kernel(int32_t T, const float *z,
+                                                           const float *a, const float *da,
+                                                           const float *dy, float *G)
+{
+    const int o = blockIdx.x, i = threadIdx.x;
+    if (o < kNnWidth) {
+        float s = 0.f, sb = 0.f;
+        for (int t = 0; t < T; ++t) {
+            const float d = da[(long long)t * kNnWidth + o];
+            s += d * z[(long long)t * kNnWidth + i];
+            sb += d;
+        }
+        G[kNnOffWa + o * kNnWidth + i] = s;
+        if (i == 0) G[kNnOffBa + o] = sb;
+    } else {
+        float s = 0.f, sb = 0.f;
+        for (int t = 0; t < T; ++t) {
+            const float at = a[(long long)t * kNnWidth + i];
+            s += dy[t] * (at > 0.f ? at : 0.f);
+            sb += dy[t];
+        }
+        G[kNnOffWb + i] = s;
+        if (i == 0) G[kNnOffBb] = sb;
+    }
+}
+
+// dP4[t][j][c] = bf16(dz[t][c] / n) where H4 > 0, else 0 (interior rows only)
+__global__ __launch_bounds__(256) void nn_dp4_kernel(const float *dz, const uint16_t *H4,
+                                                     int32_t T, int32_t n, uint16_t *dP)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)T * n * kNnWidth) return;
+    const int c = (int)(e % kNnWidth);
+    const long long m = e / kNnWidth;
+    const long long t = m / n, j = m - t * n;
+    const long long idx = (t * (n + 4) + j + 2) * kNnWidth + c;
+    const uint16_t h = H4[idx];
+    const bool on = h != 0 && !(h & 0x8000u);
+    dP[idx] = on ? bf16_bits_f32(dz[t * kNnWidth + c] / (float)n) : (uint16_t)0;
+}
+
+// ------------------------------------------------------------------------- weight gradients
+
+// Partial dW[tap][ci][co] = sum over a chunk of positions of H[row j + tap][ci] * dP[row j + 2][co]
+// (padded rows), and for tap 0 / ci block 0 the partial bias gradient sum dP[row j + 2][co].
+// Grid (chunks, taps, CI / 32). A workgroup of 256 threads covers 32 ci x 128 co: thread
+// (ci quad, co quad) = (threadIdx / 32, threadIdx % 32) holds 4 x 4 sums. Positions are staged
+// through LDS 32 at a time.
+template <int CI>
+__global__ __launch_bounds__(256) void nn_wgrad_kernel(const uint16_t *H, const uint16_t *dP,
+                                                       int32_t T, int32_t n, int32_t chunk,
+                                                       float *partW, float *partB)
+{
+    __shared__ float hs[32][32];
+    __shared__ float ps[32][kNnWidth];
+    const int tid = threadIdx.x;
+    const int tap = blockIdx.y, cib = blockIdx.z;
+    const long long M = (long long)T * n;
+    const long long p0 = (long long)blockIdx.x * chunk;
+    const long long p1 = p0 + chunk < M ? p0 + chunk : M;
+    const int cq = tid >> 5, oq = tid & 31;  // ci 4*cq .. +3 (of 32), co 4*oq .. +3
+    float acc[4][4] = {};
+    float bacc[4] = {};
+    for (long long pb = p0; pb < p1; pb += 32) {
+        // stage 32 positions: H rows (32 channels of this ci block) and dP rows (128 channels)
+        for (int e = tid; e < 32 * 32; e += 256) {
+            const int r = e >> 5, ci = e & 31;
+            const long long m = pb + r;
+            float v = 0.f;
+            if (m < p1) {
+                const long long t = m / n, j = m - t * n;
+                v = bf16_to_f32(H[(t * (n + 4) + j + tap) * CI + cib * 32 + ci]);
+            }
+            hs[r][ci] = v;
+        }
+        for (int e = tid; e < 32 * kNnWidth; e += 256) {
+            const int r = e >> 7, co = e & 127;
+            const long long m = pb + r;
+            float v = 0.f;
+            if (m < p1) {
+                const long long t = m / n, j = m - t * n;
+                v = bf16_to_f32(dP[(t * (n + 4) + j + 2) * kNnWidth + co]);
+            }
+            ps[r][co] = v;
+        }
+        __syncthreads();
+        for (int r = 0; r < 32; ++r) {
+            float hv[4], pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hv[u] = hs[r][4 * cq + u];
+                pv[u] = ps[r][4 * oq + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc[u][w] += hv[u] * pv[w];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) bacc[w] += pv[w];
+        }
+        __syncthreads();
+    }
+    float *dst = partW + (long long)blockIdx.x * (kNnTaps * CI * kNnWidth) +
+                 ((long long)tap * CI + cib * 32) * kNnWidth;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) dst[(4 * cq + u) * kNnWidth + 4 * oq + w] = acc[u][w];
+    if (tap == 0 && cib == 0 && cq == 0) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) partB[(long long)blockIdx.x * kNnWidth + 4 * oq + w] = bacc[w];
+    }
+}
+
+// G[offW + e] = sum over chunks of partW[chunk][e] (e < count), G[offB + c] likewise for the bias
+__global__ __launch_bounds__(256) void nn_wgrad_reduce_kernel(const float *partW,
+                                                              const float *partB, int32_t chunks,
+                                                              int32_t count, float *G, int32_t offW,
+                                                              int32_t offB)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < count) {
+        float s = 0.f;
+        for (int k = 0; k < chunks; ++k) s += partW[(long long)k * count + e];
+        G[offW + e] = s;
+    } else if (e < count + kNnWidth) {
+        const int c = e - count;
+        float s = 0.f;
+        for (int k = 0; k < chunks; ++k) s += partB[(long long)k * kNnWidth + c];
+        G[offB + c] = s;
+    }
+}
+
+// ------------------------------------------------------------------------- Adam and weights
+
+__global__ __launch_bounds__(256) void nn_adam_kernel(float *P, float *m, float *v, const float *G,
+                                                      int32_t count, float lr, float bc1,
+                                                      float bc2)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    const float g = G[e];
+    const float mm = 0.9f * m[e] + 0.1f * g;
+    const float vv = 0.999f * v[e] + 0.001f * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+}
+
+// bf16 copies of the conv weights: Wf_l[co][tap * CI + ci] (forward) and, for layers 2..4,
+// Wb_l[ci][tap' * 128 + co] = W_l[4 - tap'][ci][co] (backward data). One thread per weight.
+__global__ __launch_bounds__(256) void nn_pack_kernel(const float *P, NnWeights w)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    constexpr int n1 = kNnTaps * kNnCi0 * kNnWidth, nl = kNnTaps * kNnWidth * kNnWidth;
+    if (e < n1) {
+        const int tap = e / (kNnCi0 * kNnWidth), r = e % (kNnCi0 * kNnWidth);
+        const int ci = r / kNnWidth, co = r % kNnWidth;
+        w.f[0][co * (kNnTaps * kNnCi0) + tap * kNnCi0 + ci] = bf16_bits_f32(P[nn_off_w(0) + e]);
+        return;
+    }
+    const int e2 = e - n1;
+    if (e2 >= 3 * nl) return;
+    const int l = 1 + e2 / nl, r0 = e2 % nl;
+    const int tap = r0 / (kNnWidth * kNnWidth), r = r0 % (kNnWidth * kNnWidth);
+    const int ci = r / kNnWidth, co = r % kNnWidth;
+    const uint16_t b = bf16_bits_f32(P[nn_off_w(l) + r0]);
+    w.f[l][co * (kNnTaps * kNnWidth) + tap * kNnWidth + ci] = b;
+    w.b[l][ci * (kNnTaps * kNnWidth) + (kNnTaps - 1 - tap) * kNnWidth + co] = b;
+}
+
+// ------------------------------------------------------------------------- top-k
+
+__device__ __forceinline__ uint32_t nn_key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // increasing with f
+}
+
+// Histogram of the 8-bit digit `shift` of the keys whose higher digits equal sel->prefix.
+__global__ __launch_bounds__(256) void nn_topk_hist_kernel(const float *s, long long C,
+                                                           const NnSelect *sel, int shift,
+                                                           unsigned long long *hist)
+{
+    __shared__ unsigned int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t prefix = sel->prefix, pmask = sel->mask;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < C;
+         i += (long long)gridDim.x * 256) {
+        const uint32_t k = nn_key(s[i]);
+        if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// One thread: pick the digit where the running count reaches the remaining rank; clear hist.
+__global__ void nn_topk_pick_kernel(NnSelect *sel, int shift, unsigned long long *hist)
+{
+    unsigned long long below = 0;
+    int d = 0;
+    for (; d < 256; ++d) {
+        if (below + hist[d] >= sel->rank) break;
+        below += hist[d];
+    }
+    if (d > 255) d = 255;  // unreachable when rank <= the candidates left
+    sel->rank -= below;
+    sel->prefix |= (uint32_t)d << shift;
+    sel->mask |= 255u << shift;
+    for (int k = 0; k < 256; ++k) hist[k] = 0;
+}
+
+// Per block of 256 candidates: how many keys are below the threshold and how many equal it.
+__global__ __launch_bounds__(256) void nn_topk_count_kernel(const float *s, long long C,
+                                                            const NnSelect *sel,
+                                                            unsigned int *cnt)
+{
+    __shared__ unsigned int lt, eq;
+    if (threadIdx.x == 0) {
+        lt = 0;
+        eq = 0;
+    }
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < C) {
+        const uint32_t k = nn_key(s[i]);
+        if (k < sel->prefix) atomicAdd(&lt, 1u);
+        else if (k == sel->prefix) atomicAdd(&eq, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt[2 * blockIdx.x] = lt;
+        cnt[2 * blockIdx.x + 1] = eq;
+    }
+}
+
+// One workgroup: exclusive prefix of the per-block counts, in block order. Ties at the threshold
+// go to the lowest indices: a block takes min(eq, remaining ties) of them.
+__global__ __launch_bounds__(256) void nn_topk_scan_kernel(unsigned int *cnt, long long nblocks,
+                                                           const NnSelect *sel,
+                                                           unsigned long long *base)
+{
+    if (threadIdx.x != 0) return;
+    unsigned long long pos = 0, ties = sel->rank;  // equal keys still to take
+    for (long long b = 0; b < nblocks; ++b) {
+        const unsigned long long lt = cnt[2 * b], eq = cnt[2 * b + 1];
+        const unsigned long long take_eq = eq < ties ? eq : ties;
+        ties -= take_eq;
+        base[2 * b] = pos;
+        base[2 * b + 1] = take_eq;
+        pos += lt + take_eq;
+    }
+}
+
+// Write the selected indices in increasing index order.
+__global__ __launch_bounds__(256) void nn_topk_write_kernel(const float *s, long long C,
+                                                            const NnSelect *sel,
+                                                            const unsigned long long *base,
+                                                            int32_t *idx)
+{
+    __shared__ unsigned int flags[256];
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    uint32_t f = 0;
+    if (i < C) {
+        const uint32_t k = nn_key(s[i]);
+        f = k < sel->prefix ? 1u : (k == sel->prefix ? 2u : 0u);
+    }
+    flags[threadIdx.x] = f;
+    __syncthreads();
+    if (f == 0) return;
+    // rank among this block's selected entries (below first, ties by index within the quota)
+    unsigned int before = 0, eq_before = 0;
+    for (int u = 0; u < (int)threadIdx.x; ++u) {
+        if (flags[u] == 2u) ++eq_before;
+    }
+    const unsigned long long quota = base[2 * blockIdx.x + 1];
+    if (f == 2u && eq_before >= quota) return;
+    for (int u = 0; u < (int)threadIdx.x; ++u) {
+        if (flags[u] == 1u) ++before;
+        else if (flags[u] == 2u) before += 1;
+    }
+    // equal keys beyond the quota that precede this entry are not taken
+    const unsigned int skipped = eq_before > quota ? (unsigned int)(eq_before - quota) : 0u;
+    idx[base[2 * blockIdx.x] + before - skipped] = (int32_t)i;
+}
+
+// ------------------------------------------------------------------------- batches and loss
+
+// dst[b][*] = src[idx[b]][*] (tours of length n) and dlab[b] = lab[idx[b]] when lab is set
+__global__ __launch_bounds__(256) void nn_gather_kernel(const int32_t *src, const float *lab,
+                                                        const int32_t *idx, int32_t B, int32_t n,
+                                                        int32_t *dst, float *dlab)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)B * n) return;
+    const long long b = e / n, j = e - b * n;
+    const long long r = idx[b];
+    dst[e] = src[r * n + j];
+    if (lab && j == 0) dlab[b] = lab[r];
+}
+
+// *err = 1 if some id of count values lies outside 1..N
+__global__ __launch_bounds__(256) void nn_check_ids_kernel(const int32_t *ids, long long count,
+                                                           int32_t N, int32_t *err)
+{
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < count;
+         e += (long long)gridDim.x * 256) {
+        const int32_t c = ids[e];
+        if (c < 1 || c > N) atomicOr(err, 1);
+    }
+}
+
+// out[0] = (sum of terms[0..T-1], in order) / T
+__global__ void nn_loss_kernel(const float *terms, int32_t T, float *out)
+{
+    float s = 0.f;
+    for (int t = 0; t < T; ++t) s += terms[t];
+    out[0] = s / (float)T;
+}
+
+// ------------------------------------------------------------------------- launchers
+
+hipError_t nn_launch_gather(const int32_t *src, const float *lab, const int32_t *idx, int32_t B,
+                            int32_t n, int32_t *dst, float *dlab, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_gather_kernel, dim3((unsigned)(((long long)B * n + 255) / 256)),
+                       dim3(256), 0, st, src, lab, idx, B, n, dst, dlab);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_check_ids(const int32_t *ids, long long count, int32_t N, int32_t *err,
+                               hipStream_t st)
+{
+    const long long g = (count + 255) / 256;
+    hipLaunchKernelGGL(nn_check_ids_kernel, dim3((unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096)),
+                       dim3(256), 0, st, ids, count, N, err);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_loss(const float *terms, int32_t T, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_loss_kernel, dim3(1), dim3(1), 0, st, terms, T, out);
+    return hipGetLastError();
+}
+
+static inline unsigned grid_of(long long work, int per) { return (unsigned)((work + per - 1) / per); }
+
+hipError_t nn_launch_dstats(const int16_t *demand, int64_t ld, int64_t S, int32_t N, double *musd,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_dstats_kernel, dim3(N), dim3(256), 0, st, demand, ld, S, musd);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_features(const NnInstance &in, const int32_t *tours, int32_t T, int32_t n,
+                              const double *musd, int32_t Q, double L, uint16_t *X, int32_t *err,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_features_kernel, dim3(grid_of((long long)T * n, 256)), dim3(256), 0, st,
+                       in, tours, T, n, musd, Q, L, X, err);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *Wt,
+                          const float *bias, const uint16_t *mask, uint16_t *Y, int32_t T,
+                          int32_t n, hipStream_t st)
+{
+    const dim3 g(grid_of((long long)T * n, 256)), b(256);
+    if (ci == kNnCi0 && mode == 0)
+        hipLaunchKernelGGL((nn_conv_kernel<kNnCi0, 0>), g, b, 0, st, X, Wt, bias, mask, Y, T, n);
+    else if (ci == kNnWidth && mode == 0)
+        hipLaunchKernelGGL((nn_conv_kernel<kNnWidth, 0>), g, b, 0, st, X, Wt, bias, mask, Y, T, n);
+    else if (ci == kNnWidth && mode == 1)
+        hipLaunchKernelGGL((nn_conv_kernel<kNnWidth, 1>), g, b, 0, st, X, Wt, bias, mask, Y, T, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_head_fwd(const uint16_t *H4, int32_t T, int32_t n, const float *P, float *z,
+                              float *a, float *y, float *pred, double shift, double scale,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_head_fwd_kernel, dim3(T), dim3(128), 0, st, H4, T, n, P, z, a, y, pred,
+                       shift, scale);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_head_bwd(const float *labels, int32_t T, int32_t n, const float *P,
+                              const float *z, const float *a, const float *y, double shift,
+                              double scale, float *da, float *dz, float *dy, float *loss_terms,
+                              const uint16_t *H4, uint16_t *dP4, float *G, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_head_bwd_kernel, dim3(T), dim3(128), 0, st, labels, T, P, a, y, shift,
+                       scale, da, dz, dy, loss_terms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nn_head_grad_kernel, dim3(kNnWidth + 1), dim3(128), 0, st, T, z, a, da, dy,
+                       G);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nn_dp4_kernel, dim3(grid_of((long long)T * n * kNnWidth, 256)), dim3(256),
+                       0, st, dz, H4, T, n, dP4);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_wgrad(int ci, const uint16_t *H, const uint16_t *dP, int32_t T, int32_t n,
+                           int32_t chunk, int32_t chunks, float *partW, float *partB, float *G,
+                           int32_t offW, int32_t offB, hipStream_t st)
+{
+    const dim3 g(chunks, kNnTaps, ci / 32), b(256);
+    if (ci == kNnCi0)
+        hipLaunchKernelGGL(nn_wgrad_kernel<kNnCi0>, g, b, 0, st, H, dP, T, n, chunk, partW, partB);
+    else if (ci == kNnWidth)
+        hipLaunchKernelGGL(nn_wgrad_kernel<kNnWidth>, g, b, 0, st, H, dP, T, n, chunk, partW,
+                           partB);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int count = kNnTaps * ci * kNnWidth;
+    hipLaunchKernelGGL(nn_wgrad_reduce_kernel, dim3(grid_of(count + kNnWidth, 256)), dim3(256), 0,
+                       st, partW, partB, chunks, count, G, offW, offB);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_adam(float *P, float *m, float *v, const float *G, float lr, float bc1,
+                          float bc2, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_adam_kernel, dim3(grid_of(kNnParams, 256)), dim3(256), 0, st, P, m, v, G,
+                       (int32_t)kNnParams, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_pack(const float *P, const NnWeights &w, hipStream_t st)
+{
+    const long long total = (long long)kNnTaps * kNnCi0 * kNnWidth +
+                            3LL * kNnTaps * kNnWidth * kNnWidth;
+    hipLaunchKernelGGL(nn_pack_kernel, dim3(grid_of(total, 256)), dim3(256), 0, st, P, w);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_topk(const float *s, long long C, long long K, NnSelect *sel,
+                          unsigned long long *hist, unsigned int *cnt, unsigned long long *base,
+                          int32_t *idx, hipStream_t st)
+{
+    const unsigned hg = (unsigned)(C < 256LL * 1024 ? grid_of(C, 256) : 1024);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(nn_topk_hist_kernel, dim3(hg), dim3(256), 0, st, s, C, sel, shift,
+                           hist);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(nn_topk_pick_kernel, dim3(1), dim3(1), 0, st, sel, shift, hist);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const unsigned nb = grid_of(C, 256);
+    hipLaunchKernelGGL(nn_topk_count_kernel, dim3(nb), dim3(256), 0, st, s, C, sel, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nn_topk_scan_kernel, dim3(1), dim3(256), 0, st, cnt, (long long)nb, sel,
+                       base);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nn_topk_write_kernel, dim3(nb), dim3(256), 0, st, s, C, sel, base, idx);
+    (void)K;
+    return hipGetLastError();
+}
+
+}  // namespace splitgpu

@@ -13,7 +13,6 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/split.h"
 #include "split_internal.h"
 
 using namespace splitgpu;
@@ -574,6 +573,37 @@ split_status check_tuning(split_ctx *ctx, const split_tuning &t)
 }
 
 }  // namespace
+
+namespace splitgpu {
+
+int ctx_device(const split_ctx *ctx) { return ctx->device; }
+
+bool ctx_instance(const split_ctx *ctx, int32_t *N, int *kind, const int32_t **xy,
+                  const int32_t **dist, int64_t *max_arc)
+{
+    if (ctx->inst.kind < 0) return false;
+    *N = ctx->inst.N;
+    *kind = ctx->inst.kind;
+    *xy = ctx->inst.d_xy;
+    *dist = ctx->inst.d_dist;
+    *max_arc = ctx->inst.max_arc;
+    return true;
+}
+
+split_status ctx_fail(split_ctx *ctx, split_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+}  // namespace splitgpu
 
 extern "C" {
 

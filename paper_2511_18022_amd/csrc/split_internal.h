@@ -13,7 +13,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/split.h"
+
 namespace splitgpu {
+
+// Context accessors for the other host modules of the library (defined in split_host.cpp).
+int ctx_device(const split_ctx *ctx);
+// false when no instance is set
+bool ctx_instance(const split_ctx *ctx, int32_t *N, int *kind, const int32_t **xy,
+                  const int32_t **dist, int64_t *max_arc);
+// records the message as the context's last error and returns st
+split_status ctx_fail(split_ctx *ctx, split_status st, const char *fmt, ...);
 
 // "Infinity" for DP values. Host checks guarantee |DP value| + |weight| < 2^30.
 constexpr int32_t kInf = 0x3fffffff;

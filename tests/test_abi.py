@@ -10,12 +10,16 @@ import paper_2511_18022_amd as sg
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "split.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(split_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(split_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -67,3 +71,21 @@ def test_status_codes_match_header():
     text = open(HEADER).read()
     for name, val in re.findall(r"(SPLIT_E_[A-Z]+|SPLIT_OK)\s*=\s*(-?\d+)", text):
         assert getattr(sg, name) == int(val), name
+
+
+def test_nn_parameter_count_matches_header_and_oracle():
+    from oracle import nn
+    text = open(os.path.join(ROOT, "include", "split_nn.h")).read()
+    count = int(re.search(r"#define SPLIT_NN_PARAMS (\d+)", text).group(1))
+    assert count == sg.NN_PARAMS == nn.n_params()
+
+
+def test_nn_null_handles_are_rejected(lib):
+    null = ctypes.c_void_p()
+    assert lib.split_nn_create(null, 0, 1.0, None) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_predict(null, None, 1, 1, None, None) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_train(null, None, None, 1, 1, 1, 1, 1.0, 0, None, None) == sg.SPLIT_E_INVAL
+    assert lib.split_topk_smallest(null, None, 1, 1, None, None) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_screen(null, None, 1, 1, 1, None, 1, 1, 1, None, None, None, None, None,
+                               None) == sg.SPLIT_E_INVAL
+    lib.split_nn_destroy(null)

@@ -1,0 +1,266 @@
+"""GPU tests of the tour-encoder surrogate against the float64 reference (oracle/nn.py):
+features and forward pass, loss and gradient, the Adam step, deterministic training, checkpoint
+resume, top-k selection and screening with exact re-evaluation.
+
+Tolerances: the reference rounds to bfloat16 at the same points as the GPU, so the remaining
+differences come from fp32 accumulation and the bfloat16 roundings it flips (one bfloat16 unit,
+2^-8 relative, on an element whose exact value lies near a rounding boundary). Where a sum
+cancels (random-sign weights), its fp32 error relative to the result grows by the cancellation
+factor and about 1% of the stored values flip per layer; with all-positive weights nothing
+cancels and flips are rare. So:
+  - all-positive weights: outputs to 2e-5 (1 + |y|), every gradient tensor to 2e-3 of its norm,
+    at tour lengths 6 (boundary rows dominate) and 40 (measured: 3e-5 and 2.5e-4 at most);
+  - random weights: outputs to 1e-3 (1 + |y|), gradient tensors to 1e-2 of their norm (measured:
+    3e-4 and 1.3e-3 at most; W1 sits behind three backward convolutions of flipped roundings);
+  - Adam's update to fp32 rounding.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import nn as nnref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+L = 1000.0
+N, S, Q, NT, NL = 60, 512, 100, 6, 40
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import paper_2511_18022_amd as sg
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return sg
+
+
+@pytest.fixture(scope="module")
+def env(sg):
+    xy = gen.coords(21, N)
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(xy)
+    dem = gen.demand_uniform(21, N, S, 0, 30)
+    ddem = torch.from_numpy(dem).cuda()
+    tours = np.stack([gen.tour(21, N, NL, variant=v) for v in range(1, NT + 1)])
+    d = oracle.dist_matrix(xy)
+    mu, sd = nnref.demand_stats(dem)
+    Xs = [nnref.features(t, d, mu, sd, Q, L, xy=xy) for t in tours]
+    yield {"ctx": ctx, "xy": xy, "dem": dem, "ddem": ddem, "tours": tours,
+           "dtours": torch.from_numpy(tours).cuda(), "d": d, "Xs": Xs}
+    ctx.close()
+
+
+def make_net(sg, env, seed=3, shift=1000.0, scale=50.0):
+    net = sg.SplitNN(env["ctx"], seed=seed, length_scale=L)
+    net.set_scenarios(env["ddem"], Q)
+    net.set_norm(shift, scale)
+    return net
+
+
+def test_forward_matches_reference(sg, env):
+    net = make_net(sg, env)
+    p = net.params().astype(np.float64)
+    pred = net.predict(env["dtours"]).cpu().numpy().astype(np.float64)
+    y = (pred - 1000.0) / 50.0
+    y_ref = nnref.forward(p, env["Xs"], bf16=True)
+    err = np.abs(y - y_ref)
+    print(f"[nn] forward |y - y_ref| max {err.max():.3e}, |y| max {np.abs(y_ref).max():.3f}",
+          flush=True)
+    assert np.all(err <= 1e-3 * (1 + np.abs(y_ref)))
+    # a second set of parameters: trained-scale weights and nonzero biases
+    rng = np.random.default_rng(7)
+    q = p * rng.uniform(0.5, 1.5, p.size)
+    pr = nnref.unpack(q)
+    for l in range(1, 5):
+        pr[f"b{l}"] = rng.normal(0, 0.05, nnref.WIDTH)
+    pr["ba"] = rng.normal(0, 0.05, nnref.WIDTH)
+    q = nnref.pack(pr).astype(np.float32)
+    net.set_params(q)
+    y2 = (net.predict(env["dtours"]).cpu().numpy() - 1000.0) / 50.0
+    y2_ref = nnref.forward(q.astype(np.float64), env["Xs"], bf16=True)
+    err2 = np.abs(y2 - y2_ref)
+    print(f"[nn] forward (perturbed) max {err2.max():.3e}", flush=True)
+    assert np.all(err2 <= 1e-3 * (1 + np.abs(y2_ref)))
+    net.close()
+
+
+def grad_errors(g, g_ref):
+    errs, off = {}, 0
+    for name, shape in nnref.param_shapes():
+        size = int(np.prod(shape))
+        a, b = g[off:off + size].astype(np.float64), g_ref[off:off + size]
+        errs[name] = (np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30), np.linalg.norm(b))
+        off += size
+    return errs
+
+
+def positive_params(seed):
+    # all weights and biases positive: no cancellation in any sum, so fp32 and fp64 round the
+    # stored bfloat16 values the same way almost everywhere
+    rng = np.random.default_rng(seed)
+    p = nnref.unpack(np.zeros(nnref.n_params()))
+    p["W1"][:, :8, :] = rng.uniform(0.0, 0.06, (5, 8, nnref.WIDTH))
+    for l in range(2, 5):
+        p[f"W{l}"] = rng.uniform(0.0, 0.004, (5, nnref.WIDTH, nnref.WIDTH))
+    for l in range(1, 5):
+        p[f"b{l}"] = rng.uniform(0.0, 0.05, nnref.WIDTH)
+    p["Wa"] = rng.uniform(0.0, 0.02, (nnref.WIDTH, nnref.WIDTH))
+    p["ba"] = rng.uniform(0.0, 0.05, nnref.WIDTH)
+    p["wb"] = rng.uniform(0.0, 0.1, nnref.WIDTH)
+    return nnref.pack(p).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [6, NL])
+def test_gradient_matches_reference_tightly_without_cancellation(sg, env, n):
+    net = make_net(sg, env)
+    q = positive_params(n)
+    net.set_params(q)
+    tours = np.ascontiguousarray(env["tours"][:, :n])
+    Xs = [nnref.features(t, env["d"], *nnref.demand_stats(env["dem"]), Q, L, xy=env["xy"])
+          for t in tours]
+    y = (net.predict(torch.from_numpy(tours).cuda()).cpu().numpy() - 1000.0) / 50.0
+    y_ref = nnref.forward(q.astype(np.float64), Xs, bf16=True)
+    print(f"[nn] positive regime n={n}: forward max err {np.abs(y - y_ref).max():.3e}", flush=True)
+    assert np.all(np.abs(y - y_ref) <= 2e-5 * (1 + np.abs(y_ref)))
+    labels = (1000.0 + 50.0 * (y_ref - 0.5)).astype(np.float32)
+    g, loss = net.gradient(torch.from_numpy(tours).cuda(), torch.from_numpy(labels).cuda())
+    loss_ref, g_ref = nnref.loss_and_grad(q.astype(np.float64), Xs,
+                                          (labels.astype(np.float64) - 1000.0) / 50.0, bf16=True)
+    errs = grad_errors(g, g_ref)
+    print(f"[nn] positive regime n={n}: loss {loss:.6f} ref {loss_ref:.6f}; " +
+          ", ".join(f"{k} {e:.1e}" for k, (e, _) in errs.items()), flush=True)
+    assert abs(loss - loss_ref) <= 1e-4 * (1 + loss_ref)
+    for name, (e, _) in errs.items():
+        assert e <= 2e-3, name
+    net.close()
+
+
+def test_gradient_matches_reference_with_random_weights(sg, env):
+    net = make_net(sg, env)
+    p = net.params().astype(np.float64)
+    rng = np.random.default_rng(8)
+    labels = (1000.0 + 50.0 * rng.normal(0, 1, NT)).astype(np.float32)
+    g, loss = net.gradient(env["dtours"], torch.from_numpy(labels).cuda())
+    loss_ref, g_ref = nnref.loss_and_grad(p, env["Xs"], (labels.astype(np.float64) - 1000.0) / 50.0,
+                                          bf16=True)
+    errs = grad_errors(g, g_ref)
+    print(f"[nn] random weights: loss {loss:.6f} ref {loss_ref:.6f}; " +
+          ", ".join(f"{k} {e:.1e}" for k, (e, _) in errs.items()), flush=True)
+    assert abs(loss - loss_ref) <= 1e-3 * (1 + loss_ref)
+    # bfloat16 roundings flipped by fp32 summation under heavy cancellation compound over the
+    # three backward convolutions in front of W1
+    for name, (e, _) in errs.items():
+        assert e <= 1e-2, name
+    net.close()
+
+
+def test_adam_step_applies_the_reference_update(sg, env):
+    net = make_net(sg, env)
+    p = net.params()
+    labels = torch.full((NT,), 1010.0, dtype=torch.float32, device="cuda")
+    g, _ = net.gradient(env["dtours"], labels)
+    lr = 1e-3
+    net.train_step(env["dtours"], labels, lr)
+    assert net.step == 1
+    p1 = net.params().astype(np.float64)
+    p1_ref, _, _ = nnref.adam(p.astype(np.float64), np.zeros(p.size), np.zeros(p.size),
+                              g.astype(np.float64), 1, lr)
+    assert np.allclose(p1, p1_ref, rtol=1e-6, atol=1e-8)
+    net.close()
+
+
+def exact_labels(env, tours):
+    cost, stats, status = env["ctx"].eval_batch(list(tours), env["ddem"], Q)
+    assert status == [0] * len(tours)
+    return np.array([s.mean for s in stats], dtype=np.float32)
+
+
+def training_set(env, count=48):
+    tours = np.stack([gen.tour(33, N, NL, variant=v) for v in range(1, count + 1)])
+    return tours, exact_labels(env, tours)
+
+
+def test_training_is_deterministic_and_learns(sg, env):
+    tours, labels = training_set(env)
+    dt, dl = torch.from_numpy(tours).cuda(), torch.from_numpy(labels).cuda()
+    nets = []
+    for _ in range(2):
+        net = make_net(sg, env, seed=5, shift=float(labels.mean()), scale=float(labels.std()))
+        first = net.train(dt, dl, batch=8, steps=6, lr=2e-3, seed=11)
+        later = net.train(dt, dl, batch=8, steps=60, lr=2e-3, seed=11)
+        print(f"[nn] mean loss first 6 steps {first:.4f}, next 60 {later:.4f}", flush=True)
+        assert later < first
+        nets.append(net)
+    assert np.array_equal(nets[0].params(), nets[1].params())
+    assert nets[0].step == 66
+    for net in nets:
+        net.close()
+
+
+def test_checkpoint_resume_is_bitwise_identical(sg, env, tmp_path):
+    tours, labels = training_set(env)
+    dt, dl = torch.from_numpy(tours).cuda(), torch.from_numpy(labels).cuda()
+    norm = (float(labels.mean()), float(labels.std()))
+    a = make_net(sg, env, seed=9, shift=norm[0], scale=norm[1])
+    a.train(dt, dl, batch=8, steps=20, lr=1e-3, seed=4)
+    b = make_net(sg, env, seed=9, shift=norm[0], scale=norm[1])
+    b.train(dt, dl, batch=8, steps=9, lr=1e-3, seed=4)
+    path = str(tmp_path / "nn.ckpt")
+    b.save(path)
+    c = make_net(sg, env, seed=123)  # different initial weights and normalization
+    c.load(path)
+    assert c.step == 9
+    c.train(dt, dl, batch=8, steps=11, lr=1e-3, seed=4)
+    assert c.step == 20
+    assert np.array_equal(a.params(), c.params())
+    assert np.array_equal(a.predict(env["dtours"]).cpu().numpy(),
+                          c.predict(env["dtours"]).cpu().numpy())
+    with open(str(tmp_path / "junk"), "wb") as fh:
+        fh.write(b"not a checkpoint")
+    with pytest.raises(sg.SplitError) as ei:
+        c.load(str(tmp_path / "junk"))
+    assert ei.value.status == sg.SPLIT_E_INVAL
+    for net in (a, b, c):
+        net.close()
+
+
+@pytest.mark.parametrize("C,K", [(1, 1), (300, 1), (5000, 17), (5000, 256), (70000, 700),
+                                 (5000, 5000)])
+def test_topk_selects_the_smallest_with_low_index_ties(sg, env, C, K):
+    rng = np.random.default_rng(C + K)
+    scores = np.round(rng.normal(0, 3, C), 1).astype(np.float32)  # many ties, both signs
+    idx = sg.topk_smallest(env["ctx"], torch.from_numpy(scores).cuda(), K).cpu().numpy()
+    order = np.lexsort((np.arange(C), scores))
+    assert np.array_equal(idx, np.sort(order[:K]))
+
+
+def test_screen_shortlist_and_exact_means(sg, env):
+    net = make_net(sg, env, seed=2)
+    C, K = 300, 30
+    cands = np.stack([gen.tour(44, N, NL, variant=v) for v in range(1, C + 1)])
+    res = net.screen(torch.from_numpy(cands).cuda(), K, env["ddem"], Q)
+    pred = res["pred"].cpu().numpy()
+    order = np.lexsort((np.arange(C), pred))
+    assert np.array_equal(res["short_idx"], np.sort(order[:K]))
+    for k, i in enumerate(res["short_idx"]):
+        costs = oracle.split(cands[i], env["d"], env["dem"], Q)
+        assert res["short_mean"][k] == oracle.moments(costs)["mean"]
+    b = int(np.argmin(res["short_mean"]))
+    assert res["best_idx"] == res["short_idx"][b] and res["best_mean"] == res["short_mean"][b]
+    # the predictions are the ones predict() gives
+    assert np.array_equal(pred, net.predict(torch.from_numpy(cands).cuda()).cpu().numpy())
+    net.close()
+
+
+def test_bad_tour_ids_are_rejected(sg, env):
+    net = make_net(sg, env)
+    bad = env["tours"].copy()
+    bad[2, 5] = N + 7
+    with pytest.raises(sg.SplitError) as ei:
+        net.predict(torch.from_numpy(bad).cuda())
+    assert ei.value.status == sg.SPLIT_E_TOUR
+    net.close()
