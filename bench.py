@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 
 METRIC = "Split scenario-evals/s at n=1000,S=2^20 (% roofline)"
 METRIC_BATCH = "Split scenario-evals/s, 256 tours n~U[100,1000] x S=65536 (% roofline)"
+METRIC_SCREEN = "screened tours/s at regret (1000 customers, S=65536, top 1% re-evaluated)"
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 # INT32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -149,6 +151,136 @@ def timed_steps(ctx, step, wait, steps: int, warmup: int):
     return el * 1e3 / steps, kern_ms / max(launches, 1), kname, launches
 
 
+def exact_means(ctx, tours, dem, Q, chunk: int = 256):
+    """Exact expected cost (mean over the scenarios) of every tour, chunk tours per batch."""
+    import numpy as np
+    out = np.empty(len(tours))
+    t0 = last = time.perf_counter()
+    for k0 in range(0, len(tours), chunk):
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"exact evaluation: {k0} of {len(tours)} tours, {last - t0:.0f}s")
+        _, stats, status = ctx.eval_batch(tours[k0:k0 + chunk], dem, Q)
+        assert all(x == 0 for x in status)
+        out[k0:k0 + len(stats)] = [st.mean for st in stats]
+    return out
+
+
+def run_screen(args, threads):
+    """Surrogate screening against exact-only search on the same candidates."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2511_18022_amd as sg
+    t0 = time.perf_counter()
+    w = gen.make_screen_workload("screen", train=args.train, candidates=args.candidates,
+                                 threads=threads)
+    C, ntrain = len(w.cands), len(w.train)
+    log(f"generated screen: N={w.N} S={w.S} Q={w.Q}, {ntrain} training tours, {C} candidates, "
+        f"keep {w.keep} ({time.perf_counter() - t0:.1f}s)")
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    tr = torch.from_numpy(w.train).cuda()
+    ca = torch.from_numpy(w.cands).cuda()
+    tu, tune_ms, _ = ctx.autotune(list(w.cands[:256]), dem, w.Q, reps=2)
+    log(f"autotune on 256 candidates: {tu} {tune_ms:.3f} ms")
+    # labels: exact expected costs of the training tours from the GPU Split
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    labels = exact_means(ctx, w.train, dem, w.Q)
+    label_s = time.perf_counter() - t0
+    log(f"labelled {ntrain} tours in {label_s:.2f}s; mean {labels.mean():.1f} std {labels.std():.1f}")
+    net = sg.SplitNN(ctx, seed=1, length_scale=1000.0)
+    net.set_scenarios(dem, w.Q)
+    net.set_norm(float(labels.mean()), float(labels.std()))
+    lab = torch.from_numpy(labels.astype(np.float32)).cuda()
+    steps = args.epochs * (ntrain // args.batch)
+    t0 = time.perf_counter()
+    loss = net.train(tr, lab, batch=args.batch, steps=steps, lr=args.lr, seed=3)
+    train_s = time.perf_counter() - t0
+    log(f"trained {steps} steps (batch {args.batch}) in {train_s:.2f}s, mean loss {loss:.4f}")
+    # screening, timed: predict every candidate, keep the top 1%, evaluate those exactly
+    res = net.screen(ca[:min(C, 4096)], max(1, min(C, 4096) // 100), dem, w.Q)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = net.screen(ca, w.keep, dem, w.Q)
+    torch.cuda.synchronize()
+    screen_s = time.perf_counter() - t0
+    # forward pass alone (HIP events on its stream): the conv layers' MFMA rate
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    net.predict(ca, out=res["pred"])
+    e1.record()
+    torch.cuda.synchronize()
+    predict_ms = e0.elapsed_time(e1)
+    # exact-only, timed
+    t0 = time.perf_counter()
+    means = exact_means(ctx, w.cands, dem, w.Q)
+    exact_s = time.perf_counter() - t0
+    best = int(np.argmin(means))
+    regret = (res["best_mean"] - means[best]) / means[best]
+    pred = res["pred"].cpu().numpy()
+    rank_corr = float(np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(means)))[0, 1])
+    rank_of_best = int((pred < pred[best]).sum())
+    log(f"screen {screen_s:.3f}s ({C / screen_s:.0f} tours/s), exact-only {exact_s:.3f}s "
+        f"({C / exact_s:.0f} tours/s), regret {regret:.5f}, best exact mean {means[best]:.2f} at "
+        f"predicted rank {rank_of_best}, Spearman {rank_corr:.4f}")
+    n = w.N
+    flops_per_tour = 2.0 * n * 128 * (5 * 8 + 3 * 5 * 128)
+    achieved = flops_per_tour * C / (predict_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC_SCREEN,
+        "value": C / screen_s,
+        "unit": "tours/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": screen_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (surrogate), int32 (exact Split)",
+        "data": "synthetic",
+        "regret": regret,
+        "exact_only": {"tours_per_s": C / exact_s, "seconds": exact_s, "best_mean": means[best]},
+        "speedup_vs_exact_only": exact_s / screen_s,
+        "config": {"workload": "screen", "N": n, "S": w.S, "Q": w.Q, "candidates": C,
+                   "keep": w.keep, "train_tours": ntrain, "train_steps": steps,
+                   "batch": args.batch, "lr": args.lr, "train_seconds": train_s,
+                   "label_seconds": label_s, "final_mean_loss": loss,
+                   "best_screened_mean": res["best_mean"], "spearman_pred_vs_exact": rank_corr,
+                   "predicted_rank_of_exact_best": rank_of_best,
+                   "candidates_recipe": "2-opt base tour with 1..60 random segment reversals"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "surrogate forward (nn_conv_kernel x4 + head)",
+                     "kernel_avg_ms": predict_ms, "flops_per_tour": flops_per_tour},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        d = oracle.dist_matrix(w.xy)
+        k = 0
+        t0 = time.perf_counter()
+        ok = True
+        while time.perf_counter() - t0 < 15.0 and k < C:
+            m = oracle.moments(oracle.split(w.cands[k], d, w.demand, w.Q, threads=threads))["mean"]
+            ok &= m == means[k]
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": k / el, "unit": "tours/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"exact evaluation of the first {k} candidates at "
+                                         f"S={w.S}, {threads} threads, {el:.1f} s wall",
+                               "parity_vs_gpu_on_sample": bool(ok)}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    net.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +302,12 @@ def main():
                     help="skip counting the window work that sizes the ALU roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 2 GiB (HBM counter scale)")
+    ap.add_argument("--candidates", type=int, default=100_000,
+                    help="screen workload: candidate tours (the full recipe has 1,000,000)")
+    ap.add_argument("--train", type=int, default=100_000, help="screen workload: training tours")
+    ap.add_argument("--epochs", type=int, default=2, help="screen workload: training epochs")
+    ap.add_argument("--batch", type=int, default=128, help="screen workload: training batch")
+    ap.add_argument("--lr", type=float, default=1e-3, help="screen workload: Adam learning rate")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -190,6 +328,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     threads = max(1, min(16, os.cpu_count() or 1))
+    if args.workload == "screen":
+        run_screen(args, threads)
+        return
     batch = args.workload in gen.BATCH_RECIPES
     t0 = time.perf_counter()
     if batch:

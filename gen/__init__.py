@@ -51,8 +51,10 @@ def _load():
         lib.sg_demand_uniform.argtypes = [u64, i32, i64, i64, i32, i32, P, ctypes.c_int]
         lib.sg_demand_poisson.argtypes = [u64, i32, i64, i64, f64, f64, i32, P, P, ctypes.c_int]
         lib.sg_demand_copula.argtypes = [u64, i32, i64, i64, f64, f64, f64, i32, P, ctypes.c_int]
+        lib.sg_two_opt_tour.argtypes = [P, i32, i32, P]
+        lib.sg_perturb.argtypes = [u64, P, i32, i64, i32, i32, P, ctypes.c_int]
         for f in (lib.sg_coords, lib.sg_tour, lib.sg_demand_uniform, lib.sg_demand_poisson,
-                  lib.sg_demand_copula):
+                  lib.sg_demand_copula, lib.sg_two_opt_tour, lib.sg_perturb):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -208,3 +210,65 @@ def make_workload(name: str, S: int | None = None, threads=None) -> Workload:
     else:
         dem = demand_copula(seed, N, S, law[1], law[2], law[3], Q, threads=threads)
     return Workload(name, N, N, S, Q, seed, xy, t, dem)
+
+
+def two_opt_tour(xy: np.ndarray, max_passes: int = 200) -> np.ndarray:
+    """A short giant tour over all customers: nearest neighbour, then 2-opt on straight-line
+    distances (a starting point for perturbed candidates; no Split cost involved)."""
+    xy = np.ascontiguousarray(xy, dtype=np.int32)
+    N = xy.shape[0] - 1
+    t = np.zeros(N, dtype=np.int32)
+    _check(_load().sg_two_opt_tour(_ptr(xy), N, int(max_passes), _ptr(t)), "two_opt_tour")
+    return t
+
+
+def perturb(seed: int, base: np.ndarray, count: int, rmin: int, rmax: int,
+            threads=None) -> np.ndarray:
+    """[count, n] candidates: the base tour with rmin..rmax random segment reversals each."""
+    base = np.ascontiguousarray(base, dtype=np.int32)
+    out = np.empty((int(count), base.size), dtype=np.int32)
+    _check(_load().sg_perturb(seed, _ptr(base), base.size, int(count), int(rmin), int(rmax),
+                              _ptr(out), _threads(threads)), "perturb")
+    return out
+
+
+# Screening workload: one 1000-customer instance and 65,536 copula scenarios; a training set
+# and a candidate set of randomly 2-opt-perturbed copies of a short base tour (independent
+# streams), screened to the top 1%.
+SCREEN_RECIPES = {
+    "screen": dict(N=1000, S=65536, Q=500, seed=5, law=("copula", 0.6, 20.0, 0.5),
+                   train=100_000, candidates=1_000_000, rmin=1, rmax=60, keep=0.01),
+}
+
+
+@dataclass
+class ScreenWorkload:
+    name: str
+    N: int
+    S: int
+    Q: int
+    seed: int
+    xy: np.ndarray
+    base: np.ndarray
+    demand: np.ndarray
+    train: np.ndarray  # [train, N] int32
+    cands: np.ndarray  # [candidates, N] int32
+    keep: int
+
+
+def make_screen_workload(name: str = "screen", train: int | None = None,
+                         candidates: int | None = None, S: int | None = None,
+                         threads=None) -> ScreenWorkload:
+    r = SCREEN_RECIPES[name]
+    N, Q, seed = r["N"], r["Q"], r["seed"]
+    S = r["S"] if S is None else int(S)
+    ntrain = r["train"] if train is None else int(train)
+    ncand = r["candidates"] if candidates is None else int(candidates)
+    xy = coords(seed, N)
+    base = two_opt_tour(xy)
+    law = r["law"]
+    dem = demand_copula(seed, N, S, law[1], law[2], law[3], Q, threads=threads)
+    tr = perturb(seed * 1000 + 1, base, ntrain, r["rmin"], r["rmax"], threads)
+    ca = perturb(seed * 1000 + 2, base, ncand, r["rmin"], r["rmax"], threads)
+    keep = max(1, int(round(ncand * r["keep"])))
+    return ScreenWorkload(name, N, S, Q, seed, xy, base, dem, tr, ca, keep)

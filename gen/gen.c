@@ -28,6 +28,7 @@ enum {
     SG_STREAM_LAMBDA = 4,
     SG_STREAM_POISSON = 5,
     SG_STREAM_COPULA = 6,
+    SG_STREAM_PERTURB = 8,
 };
 
 void sg_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
@@ -262,4 +263,134 @@ int sg_demand_copula(uint64_t seed, int32_t N, int64_t S, int64_t ld, double rho
     jb.kind = 2; jb.seed = seed; jb.N = N; jb.ld = ld; jb.dem = dem; jb.Q = Q;
     jb.rho = rho; jb.sigma_ln = sqrt(s2); jb.mu_ln = log(mean) - 0.5 * s2;
     return run_jobs(jb, S, nthreads);
+}
+
+/* ---- candidate tours for the surrogate's training and screening ---- */
+
+static double edist(const int32_t *xy, int32_t u, int32_t v)
+{
+    const double dx = (double)xy[2 * u] - (double)xy[2 * v];
+    const double dy = (double)xy[2 * u + 1] - (double)xy[2 * v + 1];
+    return sqrt(dx * dx + dy * dy);
+}
+
+/*
+ * A short giant tour over customers 1..N: nearest neighbour from the depot, then 2-opt
+ * (reverse tour[i..j] when it shortens the closed depot-tour-depot cycle; first improvement)
+ * until a sweep improves nothing or max_passes sweeps. Straight-line double distances: this is
+ * only a good starting point for perturbed candidates, not any cost the Split computes.
+ */
+int sg_two_opt_tour(const int32_t *xy, int32_t N, int32_t max_passes, int32_t *tour)
+{
+    if (!xy || !tour || N < 1) return -1;
+    unsigned char *used = (unsigned char *)calloc((size_t)N + 1, 1);
+    if (!used) return -2;
+    int32_t cur = 0;
+    for (int32_t k = 0; k < N; ++k) {
+        int32_t best = -1;
+        double bd = 0.0;
+        for (int32_t c = 1; c <= N; ++c) {
+            if (used[c]) continue;
+            const double dd = edist(xy, cur, c);
+            if (best < 0 || dd < bd) {
+                best = c;
+                bd = dd;
+            }
+        }
+        used[best] = 1;
+        tour[k] = best;
+        cur = best;
+    }
+    free(used);
+    for (int32_t pass = 0; pass < max_passes; ++pass) {
+        int improved = 0;
+        for (int32_t i = 0; i < N - 1; ++i) {
+            const int32_t a = i > 0 ? tour[i - 1] : 0;
+            for (int32_t j = i + 1; j < N; ++j) {
+                const int32_t b = j + 1 < N ? tour[j + 1] : 0;
+                const double delta = edist(xy, a, tour[j]) + edist(xy, tour[i], b) -
+                                     edist(xy, a, tour[i]) - edist(xy, tour[j], b);
+                if (delta < -1e-9) {
+                    for (int32_t l = i, r = j; l < r; ++l, --r) {
+                        const int32_t t = tour[l];
+                        tour[l] = tour[r];
+                        tour[r] = t;
+                    }
+                    improved = 1;
+                }
+            }
+        }
+        if (!improved) break;
+    }
+    return 0;
+}
+
+typedef struct {
+    uint64_t seed;
+    const int32_t *base;
+    int32_t n, rmin, rmax;
+    int64_t c_begin, c_end;
+    int32_t *out;
+} sg_pjob;
+
+static void *sg_perturb_worker(void *arg)
+{
+    const sg_pjob *j = (const sg_pjob *)arg;
+    for (int64_t c = j->c_begin; c < j->c_end; ++c) {
+        int32_t *t = j->out + c * j->n;
+        memcpy(t, j->base, sizeof(int32_t) * (size_t)j->n);
+        uint32_t r[4];
+        draw4(j->seed, SG_STREAM_PERTURB, (uint64_t)c, 0xFFFFFFFFu, r);
+        const int32_t span = j->rmax - j->rmin + 1;
+        const int32_t moves = j->rmin + (int32_t)(((uint64_t)r[0] * (uint64_t)span) >> 32);
+        for (int32_t k = 0; k < moves; ++k) {
+            draw4(j->seed, SG_STREAM_PERTURB, (uint64_t)c, (uint32_t)k, r);
+            int32_t a = (int32_t)(((uint64_t)r[0] * (uint64_t)j->n) >> 32);
+            int32_t b = (int32_t)(((uint64_t)r[1] * (uint64_t)j->n) >> 32);
+            if (a > b) {
+                const int32_t x = a;
+                a = b;
+                b = x;
+            }
+            for (; a < b; ++a, --b) {
+                const int32_t x = t[a];
+                t[a] = t[b];
+                t[b] = x;
+            }
+        }
+    }
+    return NULL;
+}
+
+/*
+ * count candidates [count][n]: the base tour with m random segment reversals each, m uniform
+ * on {rmin..rmax}; reversal k of candidate c reverses positions [min(a,b), max(a,b)] with a, b
+ * uniform on {0..n-1} from Philox (seed, stream 8, counter (c, k)). Threads over candidates.
+ */
+int sg_perturb(uint64_t seed, const int32_t *base, int32_t n, int64_t count, int32_t rmin,
+               int32_t rmax, int32_t *out, int nthreads)
+{
+    if (!base || !out || n < 1 || count < 0 || rmin < 0 || rmax < rmin) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    pthread_t th[64];
+    sg_pjob jobs[64];
+    int started = 0;
+    for (int k = 0; k < nthreads; ++k) {
+        jobs[k].seed = seed;
+        jobs[k].base = base;
+        jobs[k].n = n;
+        jobs[k].rmin = rmin;
+        jobs[k].rmax = rmax;
+        jobs[k].c_begin = count * k / nthreads;
+        jobs[k].c_end = count * (k + 1) / nthreads;
+        jobs[k].out = out;
+        /* a thread that cannot start runs its share here */
+        if (pthread_create(&th[started], NULL, sg_perturb_worker, &jobs[k]) == 0)
+            ++started;
+        else
+            sg_perturb_worker(&jobs[k]);
+    }
+    for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+    return 0;
 }

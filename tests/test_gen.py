@@ -92,3 +92,35 @@ def test_named_workloads_small():
     assert w2.demand.shape == (200, 1000) and w2.Q == 200
     w3 = gen.make_workload("copula-n1000", S=512)
     assert w3.demand.shape == (1000, 512) and w3.Q == 500
+
+
+def _cycle_len(xy, t):
+    p = np.r_[0, t, 0]
+    return float(np.hypot(*(xy[p[1:]] - xy[p[:-1]]).T).sum())
+
+
+def test_two_opt_base_tour_is_a_short_permutation():
+    xy = gen.coords(5, 300)
+    t = gen.two_opt_tour(xy)
+    assert sorted(t.tolist()) == list(range(1, 301))
+    # 2-opt local optimum: no single reversal shortens the depot cycle
+    L = _cycle_len(xy, t)
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        i, j = sorted(rng.choice(300, 2, replace=False))
+        u = t.copy()
+        u[i:j + 1] = u[i:j + 1][::-1]
+        assert _cycle_len(xy, u) >= L - 1e-6
+    assert L < 0.2 * _cycle_len(xy, gen.tour(5, 300))
+
+
+def test_perturbed_candidates_are_permutations_and_thread_independent():
+    xy = gen.coords(6, 200)
+    base = gen.two_opt_tour(xy)
+    a = gen.perturb(11, base, 500, 1, 20, threads=1)
+    b = gen.perturb(11, base, 500, 1, 20, threads=7)
+    assert np.array_equal(a, b)
+    assert all(sorted(row.tolist()) == list(range(1, 201)) for row in a)
+    assert not np.array_equal(a, gen.perturb(12, base, 500, 1, 20))
+    # zero moves reproduce the base tour
+    assert np.array_equal(gen.perturb(11, base, 3, 0, 0), np.stack([base] * 3))
