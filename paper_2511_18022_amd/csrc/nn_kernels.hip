@@ -147,21 +147,29 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
 // ------------------------------------------------------------------------- conv (MFMA)
 
 // Y[t][j + 2][co] for M = T * n positions. A workgroup is 4 wavefronts; each wavefront computes
-// 64 positions x 128 channels: 4 x 8 tiles of 16 x 16, K = 5 * CI in steps of 32.
+// 64 positions x 128 channels: 4 x 8 tiles of 16 x 16, K = 5 * CI in blocks of 32. The weights
+// of one K block (128 co x 32, 8 KB) are staged in LDS once per workgroup, double-buffered with
+// one barrier per block; the activation fragments of the next block are loaded while the
+// current one runs. LDS holds a block as [k quarter][co] so that the 16-byte reads of the 16
+// lanes of a column group hit consecutive addresses.
 // MODE 0: Y = bf16(relu(acc + bias[co]))       (forward)
 // MODE 1: Y = bf16(acc) where mask > 0, else 0 (backward data: mask = the layer's input H)
+// Wavefronts past the last position run the loop on a clamped row (every barrier is reached)
+// and store nothing.
 template <int CI, int MODE>
 __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const uint16_t *Wt,
                                                       const float *bias, const uint16_t *mask,
                                                       uint16_t *Y, int32_t T, int32_t n)
 {
     constexpr int K = kNnTaps * CI;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    constexpr int KB = K / 32;
+    __shared__ bf16x8 Bs[2][4 * kNnWidth];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const long long M = (long long)T * n;
     const long long m0 = ((long long)blockIdx.x * 4 + wave) * 64;
-    if (m0 >= M) return;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    const int r16 = lane & 15, kq = lane >> 4;
     // A row starts (padded row j of tour t, tap 0) of this lane's 4 positions
     const bf16x8 *arow[4];
 #pragma unroll
@@ -169,27 +177,53 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
         long long m = m0 + mt * 16 + r16;
         if (m >= M) m = M - 1;  // the ragged tail reads a valid row; its result is not stored
         const long long t = m / n, j = m - t * n;
-        arow[mt] = reinterpret_cast<const bf16x8 *>(X + (t * (n + 4) + j) * CI + kq);
+        arow[mt] = reinterpret_cast<const bf16x8 *>(X + (t * (n + 4) + j) * CI + kq * 8);
     }
-    const bf16x8 *brow = reinterpret_cast<const bf16x8 *>(Wt + (long long)r16 * K + kq);
+    // this thread stages chunks c = tid and tid + 256 of each block: co = c & 127, k quarter
+    // c >> 7, i.e. Wt[co][kb * 32 + quarter * 8 .. + 8]
+    const bf16x8 *wsrc0 = reinterpret_cast<const bf16x8 *>(Wt + (long long)(tid & 127) * K +
+                                                            (tid >> 7) * 8);
+    const bf16x8 *wsrc1 = wsrc0 + 2;  // quarter + 2
+    const int wdst0 = (tid >> 7) * kNnWidth + (tid & 127), wdst1 = wdst0 + 2 * kNnWidth;
     f32x4 acc[4][8];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < K / 32; ++kb) {
-        bf16x8 a[4], b[8];
+    Bs[0][wdst0] = wsrc0[0];
+    Bs[0][wdst1] = wsrc1[0];
+    bf16x8 a[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = arow[mt][kb * 4];
+    for (int mt = 0; mt < 4; ++mt) a[mt] = arow[mt][0];
+    __syncthreads();
+    for (int kb = 0; kb < KB; ++kb) {
+        const int cur = kb & 1;
+        const bool more = kb + 1 < KB;
+        bf16x8 wn0, wn1, an[4];
+        if (more) {
+            wn0 = wsrc0[(kb + 1) * 4];
+            wn1 = wsrc1[(kb + 1) * 4];
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) b[nt] = brow[(nt * 16 * K) / 8 + kb * 4];
+            for (int mt = 0; mt < 4; ++mt) an[mt] = arow[mt][(kb + 1) * 4];
+        }
+        bf16x8 b[8];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) b[nt] = Bs[cur][kq * kNnWidth + nt * 16 + r16];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 8; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt],
                                                                       0, 0, 0);
+        if (more) {
+            Bs[cur ^ 1][wdst0] = wn0;
+            Bs[cur ^ 1][wdst1] = wn1;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+        }
+        __syncthreads();
     }
+    if (m0 >= M) return;
     // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -216,28 +250,46 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
 
 // ------------------------------------------------------------------------- pool and head
 
-// One workgroup of 128 threads per tour: z = mean over positions of H4, a = Wa z + ba,
-// u = relu(a), y = wb . u + bb (fixed-order tree), pred = y * scale + shift.
-__global__ __launch_bounds__(128) void nn_head_fwd_kernel(const uint16_t *H4, int32_t T,
+// One workgroup of 256 threads per tour: z = mean over positions of H4, a = Wa z + ba,
+// u = relu(a), y = wb . u + bb, pred = y * scale + shift. Thread (r, g) = (tid / 16, tid % 16)
+// sums channels 8g .. 8g+7 over positions r, r + 16, ... with 16-byte loads; the 16 partial
+// sums of a channel are then added in order r = 0..15 (a fixed order: bitwise reproducible).
+__global__ __launch_bounds__(256) void nn_head_fwd_kernel(const uint16_t *H4, int32_t T,
                                                           int32_t n, const float *P, float *z,
                                                           float *a, float *y, float *pred,
                                                           double shift, double scale)
 {
+    __shared__ float part[16][kNnWidth];
     __shared__ float zs[kNnWidth];
     __shared__ float red[kNnWidth];
-    const int t = blockIdx.x, c = threadIdx.x;
-    const uint16_t *h = H4 + ((long long)t * (n + 4) + 2) * kNnWidth + c;
-    float s = 0.f;
-    for (int j = 0; j < n; ++j) s += bf16_to_f32(h[(long long)j * kNnWidth]);
-    const float zc = s / (float)n;
-    zs[c] = zc;
-    z[(long long)t * kNnWidth + c] = zc;
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int r = tid >> 4, g = tid & 15;
+    const u16x8 *h = reinterpret_cast<const u16x8 *>(H4 + ((long long)t * (n + 4) + 2) * kNnWidth) + g;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j = r; j < n; j += 16) {
+        const u16x8 v = h[(long long)j * (kNnWidth / 8)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += bf16_to_f32(v[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) part[r][8 * g + e] = s[e];
     __syncthreads();
-    const float *Wa = P + kNnOffWa;
-    float acc = P[kNnOffBa + c];
-    for (int i = 0; i < kNnWidth; ++i) acc += Wa[c * kNnWidth + i] * zs[i];
-    a[(long long)t * kNnWidth + c] = acc;
-    red[c] = P[kNnOffWb + c] * (acc > 0.f ? acc : 0.f);
+    const int c = tid;
+    if (c < kNnWidth) {
+        float sum = 0.f;
+        for (int k = 0; k < 16; ++k) sum += part[k][c];
+        const float zc = sum / (float)n;
+        zs[c] = zc;
+        z[(long long)t * kNnWidth + c] = zc;
+    }
+    __syncthreads();
+    if (c < kNnWidth) {
+        const float *Wa = P + kNnOffWa;
+        float acc = P[kNnOffBa + c];
+        for (int i = 0; i < kNnWidth; ++i) acc += Wa[c * kNnWidth + i] * zs[i];
+        a[(long long)t * kNnWidth + c] = acc;
+        red[c] = P[kNnOffWb + c] * (acc > 0.f ? acc : 0.f);
+    }
     __syncthreads();
     for (int off = 64; off > 0; off >>= 1) {
         if (c < off) red[c] += red[c + off];
@@ -664,7 +716,7 @@ hipError_t nn_launch_head_fwd(const uint16_t *H4, int32_t T, int32_t n, const fl
                               float *a, float *y, float *pred, double shift, double scale,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(nn_head_fwd_kernel, dim3(T), dim3(128), 0, st, H4, T, n, P, z, a, y, pred,
+    hipLaunchKernelGGL(nn_head_fwd_kernel, dim3(T), dim3(256), 0, st, H4, T, n, P, z, a, y, pred,
                        shift, scale);
     return hipGetLastError();
 }
