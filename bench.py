@@ -29,6 +29,7 @@ METRIC = "Split scenario-evals/s at n=1000,S=2^20 (% roofline)"
 METRIC_BATCH = "Split scenario-evals/s, 256 tours n~U[100,1000] x S=65536 (% roofline)"
 METRIC_SCREEN = "screened tours/s at regret (1000 customers, S=65536, top 1% re-evaluated)"
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+METRIC_SEARCH = "expected cost after a timed local search (1000 customers, 10^4 in-sample scenarios)"
 HBM_PEAK_GBS = 8000.0
 # INT32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -281,6 +282,89 @@ def run_screen(args, threads):
     ctx.close()
 
 
+def run_search(args, threads):
+    """Exact-only and surrogate-assisted local search under the same wall-clock budget, then an
+    out-of-sample evaluation of the start and the two results on held-out scenarios."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2511_18022_amd as sg
+    S_in, S_out = args.search_scenarios, args.holdout_scenarios
+    w = gen.make_screen_workload("screen", train=args.train, candidates=1, S=S_in, threads=threads)
+    law = gen.SCREEN_RECIPES["screen"]["law"]
+    t0 = time.perf_counter()
+    held = gen.demand_copula(w.seed + 1000, w.N, S_out, law[1], law[2], law[3], w.Q,
+                             threads=threads)
+    log(f"search: N={w.N}, {S_in} in-sample scenarios, {S_out} held-out (generated in "
+        f"{time.perf_counter() - t0:.1f}s), budget {args.budget}s per search")
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    base = w.base
+    tu, _, _ = ctx.autotune([base] * args.search_batch, dem, w.Q, reps=2)
+    log(f"autotune: {tu}")
+    exact = sg.search(ctx, base, dem, w.Q, batch=args.search_batch, budget_s=args.budget,
+                      seed=21)
+    log(f"exact-only search: {exact['iterations']} iterations, {exact['evaluated']} exact "
+        f"evaluations, {exact['start_mean']:.2f} -> {exact['best_mean']:.2f}")
+    # surrogate trained on the in-sample scenarios
+    tr = torch.from_numpy(w.train).cuda()
+    t0 = time.perf_counter()
+    labels = exact_means(ctx, w.train, dem, w.Q)
+    nn = sg.SplitNN(ctx, seed=1, length_scale=1000.0)
+    nn.set_scenarios(dem, w.Q)
+    nn.set_norm(float(labels.mean()), float(labels.std()))
+    steps = args.epochs * (len(w.train) // args.batch)
+    nn.train(tr, torch.from_numpy(labels.astype(np.float32)).cuda(), batch=args.batch,
+             steps=steps, lr=args.lr, seed=3)
+    prep_s = time.perf_counter() - t0
+    log(f"surrogate: labels and {steps} training steps in {prep_s:.1f}s")
+    assisted = sg.search(ctx, base, dem, w.Q, batch=args.search_batch, pool=args.search_pool,
+                         nn=nn, budget_s=args.budget, seed=21)
+    log(f"surrogate search: {assisted['iterations']} iterations, {assisted['predicted']} "
+        f"predicted, {assisted['evaluated']} exact, {assisted['start_mean']:.2f} -> "
+        f"{assisted['best_mean']:.2f}")
+    hdem = torch.from_numpy(held).cuda()
+    oos = {}
+    for name, t in (("start", base), ("exact_only", exact["best_tour"]),
+                    ("surrogate", assisted["best_tour"])):
+        _, st = ctx.eval(t, hdem, w.Q)
+        oos[name] = st.mean
+    log(f"out-of-sample means: {oos}")
+
+    def summary(r):
+        return {k: r[k] for k in ("iterations", "evaluated", "predicted", "improvements",
+                                  "start_mean", "best_mean", "seconds")}
+    out = {
+        "metric": METRIC_SEARCH,
+        "value": assisted["best_mean"],
+        "unit": "expected cost (in-sample mean)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": assisted["seconds"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 (exact Split), bf16 (surrogate)",
+        "data": "synthetic",
+        "exact_only": summary(exact),
+        "surrogate": summary(assisted),
+        "out_of_sample": {"scenarios": S_out, **oos},
+        "config": {"workload": "search", "N": w.N, "S": S_in, "Q": w.Q, "budget_s": args.budget,
+                   "batch": args.search_batch, "pool": args.search_pool,
+                   "surrogate_prep_seconds": prep_s, "train_tours": len(w.train),
+                   "start": "nearest neighbour + 2-opt tour (straight-line distances)",
+                   "moves": "2-opt or relocate, uniform positions"},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    nn.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +392,13 @@ def main():
     ap.add_argument("--epochs", type=int, default=2, help="screen workload: training epochs")
     ap.add_argument("--batch", type=int, default=128, help="screen workload: training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="screen workload: Adam learning rate")
+    ap.add_argument("--budget", type=float, default=10.0, help="search workload: seconds per search")
+    ap.add_argument("--search-batch", type=int, default=256,
+                    help="search workload: tours evaluated exactly per iteration")
+    ap.add_argument("--search-pool", type=int, default=4096,
+                    help="search workload: neighbours scored by the surrogate per iteration")
+    ap.add_argument("--search-scenarios", type=int, default=10_000)
+    ap.add_argument("--holdout-scenarios", type=int, default=1 << 20)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -330,6 +421,9 @@ def main():
     threads = max(1, min(16, os.cpu_count() or 1))
     if args.workload == "screen":
         run_screen(args, threads)
+        return
+    if args.workload == "search":
+        run_search(args, threads)
         return
     batch = args.workload in gen.BATCH_RECIPES
     t0 = time.perf_counter()

@@ -33,6 +33,8 @@ EXPORTED = [
     "split_nn_set_norm", "split_nn_set_scenarios", "split_nn_predict", "split_nn_gradient",
     "split_nn_train_step", "split_nn_train", "split_nn_step", "split_nn_save", "split_nn_load",
     "split_topk_smallest", "split_nn_screen",
+    # include/split_search.h
+    "split_search",
 ]
 NN_PARAMS = 283393
 VOID_FUNCS = ("split_ctx_destroy", "split_last_error", "split_graph_destroy", "split_nn_destroy")
@@ -69,6 +71,13 @@ class SplitTuning:
     @staticmethod
     def from_c(c: SplitTuningC) -> "SplitTuning":
         return SplitTuning(int(c.form), int(c.lane_per_cu), int(c.order), int(c.wave_grid))
+
+
+class SplitSearchResultC(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("evaluated", ctypes.c_int64),
+                ("predicted", ctypes.c_int64), ("improvements", ctypes.c_int64),
+                ("start_mean", ctypes.c_double), ("best_mean", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
 
 @dataclass
@@ -136,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     lib.split_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.split_nn_load.argtypes = [P, ctypes.c_char_p]
     lib.split_topk_smallest.argtypes = [P, P, i64, i64, P, P]
+    lib.split_search.argtypes = [P, P, P, i32, P, i64, i64, i32, i32, i32, f64, i64, u64, P, P,
+                                 P, i32, P, P, P]
     lib.split_nn_screen.argtypes = [P, P, i64, i32, i64, P, i64, i64, i32, P, P, P,
                                     ctypes.POINTER(i64), ctypes.POINTER(f64), P]
     for name in EXPORTED:
@@ -611,3 +622,33 @@ def topk_smallest(ctx: SplitContext, scores, K: int, stream=None):
                                             int(K), ctypes.c_void_p(idx.data_ptr()),
                                             ctypes.c_void_p(s.cuda_stream)))
     return idx
+
+
+def search(ctx: SplitContext, tour0, demand, Q: int, batch: int, budget_s: float,
+           pool: int | None = None, nn: SplitNN | None = None, max_iters: int = 1 << 62,
+           seed: int = 0, S: int | None = None, trace_cap: int = 100000, stream=None):
+    """Local search from tour0 with the exact expected cost (split_search). Returns a dict with
+    best_tour, the result fields and the (seconds, mean) trace of accepted moves."""
+    import torch
+    np = _np()
+    t0 = np.ascontiguousarray(tour0, dtype=np.int32)
+    ld, S = _demand_shape(demand, S, t0, ctx.N)
+    if demand.shape[0] < ctx.N:
+        raise ValueError("the demand tensor needs a row for every customer 1..N")
+    pool = batch if pool is None else int(pool)
+    best = np.zeros_like(t0)
+    tt = np.zeros(trace_cap)
+    tm = np.zeros(trace_cap)
+    tl = ctypes.c_int32()
+    res = SplitSearchResultC()
+    s = torch.cuda.current_stream(demand.device) if stream is None else stream
+    ctx._check(ctx._lib.split_search(
+        ctx._h, nn._h if nn is not None else None, t0.ctypes.data_as(ctypes.c_void_p), t0.size,
+        ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q), int(batch), pool, float(budget_s),
+        int(max_iters), int(seed), best.ctypes.data_as(ctypes.c_void_p),
+        tt.ctypes.data_as(ctypes.c_void_p), tm.ctypes.data_as(ctypes.c_void_p), int(trace_cap),
+        ctypes.byref(tl), ctypes.byref(res), ctypes.c_void_p(s.cuda_stream)))
+    out = {f: getattr(res, f) for f, _ in SplitSearchResultC._fields_}
+    out["best_tour"] = best
+    out["trace"] = list(zip(tt[:tl.value].tolist(), tm[:tl.value].tolist()))
+    return out

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsplitgpu.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("split_kernels.hip", "split_host.cpp", "nn_kernels.hip", "nn_host.cpp")]
+           ("split_kernels.hip", "split_host.cpp", "nn_kernels.hip", "nn_host.cpp",
+            "search_host.cpp")]
 ARCH = os.environ.get("SPLITGPU_ARCH", "gfx950")
 
 

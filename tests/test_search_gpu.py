@@ -1,0 +1,95 @@
+"""GPU tests of the local search (split_search): every reported mean is the oracle's exact
+expected cost of the reported tour, the trace only improves, and runs are deterministic for a
+fixed iteration count, with and without the surrogate's shortlist."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N, S, Q = 80, 2000, 120
+
+
+@pytest.fixture(scope="module")
+def env():
+    import paper_2511_18022_amd as sg
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    xy = gen.coords(31, N)
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(xy)
+    dem = gen.demand_uniform(31, N, S, 0, 25)
+    d = oracle.dist_matrix(xy)
+    # a weak start (a random tour) so that the search has room to improve
+    tour0 = gen.tour(31, N)
+    yield {"sg": sg, "ctx": ctx, "dem": dem, "ddem": torch.from_numpy(dem).cuda(), "d": d,
+           "tour0": tour0}
+    ctx.close()
+
+
+def exact_mean(env, tour):
+    return oracle.moments(oracle.split(tour, env["d"], env["dem"], Q))["mean"]
+
+
+def check_result(env, r, batch):
+    t = r["best_tour"]
+    assert sorted(t.tolist()) == list(range(1, N + 1))
+    assert r["start_mean"] == exact_mean(env, env["tour0"])
+    assert r["best_mean"] == exact_mean(env, t)
+    assert r["best_mean"] <= r["start_mean"]
+    assert r["evaluated"] == 1 + r["iterations"] * batch
+    means = [m for _, m in r["trace"]]
+    assert means[0] == r["start_mean"] and means[-1] == r["best_mean"]
+    assert all(b < a for a, b in zip(means, means[1:]))
+    assert len(means) == r["improvements"] + 1
+
+
+def test_exact_search_improves_and_is_deterministic(env):
+    sg = env["sg"]
+    runs = [sg.search(env["ctx"], env["tour0"], env["ddem"], Q, batch=32, budget_s=60.0,
+                      max_iters=25, seed=7) for _ in range(2)]
+    for r in runs:
+        print(f"[search] exact: {r['iterations']} iterations, {r['improvements']} improvements, "
+              f"{r['start_mean']:.1f} -> {r['best_mean']:.1f}", flush=True)
+        check_result(env, r, 32)
+        assert r["iterations"] == 25 and r["improvements"] > 0
+    assert np.array_equal(runs[0]["best_tour"], runs[1]["best_tour"])
+
+
+def test_surrogate_search_shortlists_a_pool(env):
+    sg = env["sg"]
+    nn = sg.SplitNN(env["ctx"], seed=4, length_scale=1000.0)
+    nn.set_scenarios(env["ddem"], Q)
+    m0 = exact_mean(env, env["tour0"])
+    nn.set_norm(m0, 0.05 * m0)
+    r = sg.search(env["ctx"], env["tour0"], env["ddem"], Q, batch=16, pool=128, nn=nn,
+                  budget_s=60.0, max_iters=12, seed=9)
+    print(f"[search] surrogate: {r['improvements']} improvements, {r['start_mean']:.1f} -> "
+          f"{r['best_mean']:.1f}", flush=True)
+    check_result(env, r, 16)
+    assert r["predicted"] == 12 * 128
+    nn.close()
+
+
+def test_time_budget_stops_the_search(env):
+    sg = env["sg"]
+    r = sg.search(env["ctx"], env["tour0"], env["ddem"], Q, batch=8, budget_s=0.0, seed=1)
+    assert r["iterations"] == 0 and r["best_mean"] == r["start_mean"]
+    assert np.array_equal(r["best_tour"], env["tour0"])
+
+
+def test_search_argument_errors(env):
+    sg = env["sg"]
+    for kw, code in [(dict(batch=8, pool=16), sg.SPLIT_E_INVAL),  # a pool needs a surrogate
+                     (dict(batch=0), sg.SPLIT_E_INVAL)]:
+        with pytest.raises(sg.SplitError) as ei:
+            sg.search(env["ctx"], env["tour0"], env["ddem"], Q, budget_s=1.0, **kw)
+        assert ei.value.status == code
+    bad = env["tour0"].copy()
+    bad[3] = bad[4]
+    with pytest.raises(sg.SplitError) as ei:
+        sg.search(env["ctx"], bad, env["ddem"], Q, batch=4, budget_s=1.0)
+    assert ei.value.status == sg.SPLIT_E_TOUR
