@@ -372,7 +372,7 @@ def main():
     # the GPU's clocks need a few tens of milliseconds of work to settle
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="copula-n1000")
-    ap.add_argument("--form", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--form", default="auto", choices=["auto", "lane", "wave", "mask"])
     ap.add_argument("--tours", type=int, default=None, help="batch workloads: number of tours")
     ap.add_argument("--launch", default=None, choices=["eager", "graph"],
                     help="time eager calls or replays of a captured graph (default: graph for "

@@ -42,11 +42,16 @@ typedef enum {
     SPLIT_E_NOMEM = -6   /* device or host allocation failed */
 } split_status;
 
-/* Kernel form used by split_eval (both compute identical results). */
+/* Kernel form used by split_eval (all compute identical results). */
 typedef enum {
     SPLIT_FORM_AUTO = 0, /* scenario-per-lane for large S, wavefront-per-scenario for small S */
     SPLIT_FORM_LANE = 1, /* one scenario per lane; sliding-window minimum in LDS */
-    SPLIT_FORM_WAVE = 2  /* one scenario per wavefront; lanes over predecessors p */
+    SPLIT_FORM_WAVE = 2, /* one scenario per wavefront; lanes over predecessors p */
+    SPLIT_FORM_MASK = 3  /* ablation, the two-kernel form of Section 3: the Eq. (2) window starts
+                            of every state and scenario are written to an int16 matrix in device
+                            memory (library-owned, 2 bytes per position and scenario), then a
+                            second kernel scans each window (Eq. (3)). Not used by AUTO, the
+                            autotuner or graphs. */
 } split_form;
 
 /*
@@ -133,8 +138,8 @@ split_status split_stats_get(split_ctx *ctx, split_stats *stats);
  *  stats     HOST [T] or NULL; tour_status HOST int32 [T] or NULL (per tour SPLIT_OK or
  *            SPLIT_E_DEMAND). If either is non-NULL the call blocks until both are filled; if
  *            both are NULL the call only enqueues work (split_batch_stats_get collects them).
- * Work is ordered by decreasing tour length over persistent workgroups. The library copies
- * the tours; enqueued work reads `demand` and writes `cost` until the stream reaches it.
+ * Work items are scheduled as the context's launch choices say (split_tuning). The library
+ * copies the tours; enqueued work reads `demand` and writes `cost` until the stream reaches it.
  * Errors: as split_eval (SPLIT_E_TOUR names the tour), SPLIT_E_INVAL also when
  * T * ceil(S / 64) >= 2^31; SPLIT_E_DEMAND when some tour's status is SPLIT_E_DEMAND.
  */

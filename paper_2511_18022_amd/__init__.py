@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libsplitgpu.so")
 
 SPLIT_OK, SPLIT_E_INVAL, SPLIT_E_TOUR, SPLIT_E_DEMAND = 0, -1, -2, -3
 SPLIT_E_RANGE, SPLIT_E_HIP, SPLIT_E_NOMEM = -4, -5, -6
-FORM_AUTO, FORM_LANE, FORM_WAVE = 0, 1, 2
-FORMS = {"auto": FORM_AUTO, "lane": FORM_LANE, "wave": FORM_WAVE}
+FORM_AUTO, FORM_LANE, FORM_WAVE, FORM_MASK = 0, 1, 2, 3
+FORMS = {"auto": FORM_AUTO, "lane": FORM_LANE, "wave": FORM_WAVE, "mask": FORM_MASK}
 STATUS_NAMES = {0: "SPLIT_OK", -1: "SPLIT_E_INVAL", -2: "SPLIT_E_TOUR", -3: "SPLIT_E_DEMAND",
                 -4: "SPLIT_E_RANGE", -5: "SPLIT_E_HIP", -6: "SPLIT_E_NOMEM"}
 

@@ -39,6 +39,8 @@ struct EvalBuffers {
     unsigned long long *d_partials = nullptr;
     int64_t cap_partials = 0;
     BatchCtl *d_ctl = nullptr;
+    int16_t *d_mask = nullptr;  // two-kernel form only: window starts [positions][S]
+    int64_t cap_mask = 0;       // elements
 };
 
 void free_buffers(EvalBuffers &b)
@@ -50,6 +52,7 @@ void free_buffers(EvalBuffers &b)
     if (b.d_stats) (void)hipFree(b.d_stats);
     if (b.d_partials) (void)hipFree(b.d_partials);
     if (b.d_ctl) (void)hipFree(b.d_ctl);
+    if (b.d_mask) (void)hipFree(b.d_mask);
     b = EvalBuffers();
 }
 
@@ -496,6 +499,12 @@ split_status enqueue_kernels(split_ctx *ctx, const Instance &in, const EvalBuffe
         ctx->tname = wave_kernel_name();
         HIP_TRY(ctx, launch_wave_all(ea, stream));
         if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
+    } else if (p.form == SPLIT_FORM_MASK) {
+        ctx->tname = mask_kernel_name();
+        HIP_TRY(ctx, launch_mask(ea, b.d_mask, S, stream));
+        HIP_TRY(ctx, launch_masked_dp(ea, b.d_mask, S, stream));
+        if (stop) HIP_TRY(ctx, hipEventRecord(stop, stream));
+        HIP_TRY(ctx, launch_wave_fallback(ea, stream));
     } else {
         ctx->tname = lane_kernel_name();
         HIP_TRY(ctx, launch_lane(ea, stream));
@@ -549,6 +558,18 @@ split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
     ctx->stage_ev_used[slot] = true;
 
     const Plan p = make_plan(ctx, ctx->tuning, S, ld, T, bi.maxn, bi.max_id);
+    if (p.form == SPLIT_FORM_MASK && (__int128)ctx->buf.cap_pos * S > ctx->buf.cap_mask) {
+        // one int16 window start per (position row, scenario)
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        if (ctx->buf.d_mask) (void)hipFree(ctx->buf.d_mask);
+        ctx->buf.d_mask = nullptr;
+        ctx->buf.cap_mask = 0;
+        const int64_t elems = ctx->buf.cap_pos * S;
+        if (hipMalloc(&ctx->buf.d_mask, sizeof(int16_t) * (size_t)elems) != hipSuccess)
+            return fail(ctx, SPLIT_E_NOMEM, "%s: the two-kernel form's %lld-byte mask matrix "
+                        "could not be allocated", who, (long long)(2 * elems));
+        ctx->buf.cap_mask = elems;
+    }
     st = enqueue_kernels(ctx, ctx->inst, ctx->buf, L, p, demand, S, ld, Q, cost, ldc, stream, true);
     if (st != SPLIT_OK) return st;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_stats, ctx->buf.d_stats, sizeof(DevStats) * (size_t)T,
@@ -562,7 +583,8 @@ split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
 
 split_status check_tuning(split_ctx *ctx, const split_tuning &t)
 {
-    if (t.form != SPLIT_FORM_AUTO && t.form != SPLIT_FORM_LANE && t.form != SPLIT_FORM_WAVE)
+    if (t.form != SPLIT_FORM_AUTO && t.form != SPLIT_FORM_LANE && t.form != SPLIT_FORM_WAVE &&
+        t.form != SPLIT_FORM_MASK)
         return fail(ctx, SPLIT_E_INVAL, "tuning: unknown form %d", t.form);
     if (t.lane_per_cu < 0 || t.lane_per_cu > kMaxLanePerCu)
         return fail(ctx, SPLIT_E_INVAL, "tuning: lane_per_cu must be in 0..%d", kMaxLanePerCu);
@@ -769,7 +791,8 @@ split_status split_stats_get(split_ctx *ctx, split_stats *stats)
 split_status split_set_form(split_ctx *ctx, int form)
 {
     if (!ctx) return SPLIT_E_INVAL;
-    if (form != SPLIT_FORM_AUTO && form != SPLIT_FORM_LANE && form != SPLIT_FORM_WAVE)
+    if (form != SPLIT_FORM_AUTO && form != SPLIT_FORM_LANE && form != SPLIT_FORM_WAVE &&
+        form != SPLIT_FORM_MASK)
         return fail(ctx, SPLIT_E_INVAL, "split_set_form: unknown form %d", form);
     ctx->tuning.form = form;
     return SPLIT_OK;
@@ -1020,6 +1043,9 @@ split_status split_graph_create(split_ctx *ctx, int32_t max_T, int64_t max_total
     if (st != SPLIT_OK) return bail(st);
     // any tour of the instance: lengths up to N, ids up to N
     gr->plan = make_plan(ctx, ctx->tuning, S, ld, max_T, N, N);
+    if (gr->plan.form == SPLIT_FORM_MASK)
+        return bail(fail(ctx, SPLIT_E_INVAL, "split_graph_create: the two-kernel form is an "
+                         "ablation and is not captured"));
     if (hipStreamCreateWithFlags(&gr->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         gr->cap_stream = nullptr;
         return bail(fail(ctx, SPLIT_E_HIP, "split_graph_create: hipStreamCreate failed"));

@@ -125,6 +125,11 @@ hipError_t launch_lane(const EvalArgs &a, hipStream_t stream);
 hipError_t launch_wave_all(const EvalArgs &a, hipStream_t stream);
 hipError_t launch_wave_fallback(const EvalArgs &a, hipStream_t stream);
 hipError_t launch_moments(const MomentArgs &a, hipStream_t stream);
+// two-kernel form: mask int16 [rows][mask_ld], row abase(t) + i
+hipError_t launch_mask(const EvalArgs &a, int16_t *mask, long long mask_ld, hipStream_t stream);
+hipError_t launch_masked_dp(const EvalArgs &a, const int16_t *mask, long long mask_ld,
+                            hipStream_t stream);
+const char *mask_kernel_name();
 int32_t moment_blocks(int64_t S);
 const char *lane_kernel_name();
 const char *wave_kernel_name();

@@ -750,6 +750,90 @@ __global__ __launch_bounds__(64) void split_wave_kernel(EvalArgs a, int mode)
     }
 }
 
+// ------------------------------------------------------------------------- two-kernel form
+
+// The paper's literal two-kernel form, kept as an ablation of the fused lane kernel: first the
+// Eq. (2) window starts of every (state, scenario) are written to an int16 matrix in HBM
+// (row abase(t) + i, scenario fastest), then a second kernel reads them back and takes each
+// window's minimum by scanning it.
+
+// One lane per scenario of work item (tour, 64-scenario block): prefix loads with a two-pointer;
+// mask = smallest p with P_i - P_p <= Q (p == i when q_i > Q: the window is empty).
+__global__ __launch_bounds__(64) void split_mask_kernel(EvalArgs a, int16_t *mask,
+                                                        long long mask_ld)
+{
+    const long long nsb = (a.S + 63) / 64;
+    const long long k = blockIdx.x;
+    const long long T = *a.tour.nt;
+    if (k >= nsb * T) return;
+    const int t = (int)(k / nsb);
+    const long long scen = (k - (long long)t * nsb) * 64 + threadIdx.x;
+    if (scen >= a.S) return;
+    const int64_t ab = tour_abase(a.tour.tptr, t);
+    const int n = (int)(a.tour.tptr[t + 1] - a.tour.tptr[t]);
+    const int64_t *rowoff = a.tour.rowoff + ab;
+    const char *dem = reinterpret_cast<const char *>(a.demand + scen);
+    int P = 0, Ps = 0, s = 0;
+    for (int i = 1; i <= n; ++i) {
+        P += *(const uint16_t *)(dem + rowoff[i]);
+        while (s < i && P - Ps > a.Q) {
+            ++s;
+            Ps += *(const uint16_t *)(dem + rowoff[s]);
+        }
+        mask[(ab + i) * mask_ld + scen] = (int16_t)s;
+    }
+}
+
+// One lane per scenario: g_i = w_i + min of g over [mask_i, i - 1], scanning the window in a
+// 64-entry history of g per lane in LDS. A window longer than 63 states sends the scenario to
+// the general kernel (cost marked kCostOvf); an empty window reports an infeasible demand.
+__global__ __launch_bounds__(64) void split_masked_dp_kernel(EvalArgs a, const int16_t *mask,
+                                                             long long mask_ld)
+{
+    __shared__ int ring[64][64];
+    const int lane = threadIdx.x;
+    const long long nsb = (a.S + 63) / 64;
+    const long long k = blockIdx.x;
+    const long long T = *a.tour.nt;
+    if (k >= nsb * T) return;
+    const int t = (int)(k / nsb);
+    const long long scen_raw = (k - (long long)t * nsb) * 64 + lane;
+    const bool active = scen_raw < a.S;
+    const long long scen = active ? scen_raw : a.S - 1;
+    const int64_t ab = tour_abase(a.tour.tptr, t);
+    const int n = (int)(a.tour.tptr[t + 1] - a.tour.tptr[t]);
+    const int32_t *w = a.tour.w + ab;
+    bool err = false, ovf = false;
+    int g = w[0];
+    ring[0][lane] = g;
+    for (int i = 1; i <= n; ++i) {
+        int s = mask[(ab + i) * mask_ld + scen];
+        err |= s >= i;
+        ovf |= i - s > 63;
+        if (s < i - 63) s = i - 63;
+        // uniform trip count: the longest window of the wavefront (at most 63)
+        int len = i - s;
+        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+        int m = kInf;
+        for (int d = 1; d <= len; ++d) {
+            const int p = i - d;
+            if (p >= s) m = min(m, ring[p & 63][lane]);
+        }
+        g = w[i] + m;
+        ring[i & 63][lane] = g;
+    }
+    if (!active) return;
+    if (ovf) {
+        a.cost[(long long)t * a.ldc + scen] = kCostOvf;
+        atomicAdd(&a.stats[t].ovf_count, 1);
+        atomicAdd(&a.ctl->ovf_total, 1u);
+    } else if (err) {
+        atomicOr(&a.stats[t].err_demand, 1);
+    } else {
+        a.cost[(long long)t * a.ldc + scen] = g;
+    }
+}
+
 // ------------------------------------------------------------------------- moments
 
 __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi,
@@ -870,6 +954,25 @@ hipError_t launch_wave_fallback(const EvalArgs &a, hipStream_t stream)
                        a, 1);
     return hipGetLastError();
 }
+
+hipError_t launch_mask(const EvalArgs &a, int16_t *mask, long long mask_ld, hipStream_t stream)
+{
+    const long long items = (a.S + 63) / 64 * a.tour.T_grid;
+    hipLaunchKernelGGL(split_mask_kernel, dim3((unsigned)items), dim3(64), 0, stream, a, mask,
+                       mask_ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_masked_dp(const EvalArgs &a, const int16_t *mask, long long mask_ld,
+                            hipStream_t stream)
+{
+    const long long items = (a.S + 63) / 64 * a.tour.T_grid;
+    hipLaunchKernelGGL(split_masked_dp_kernel, dim3((unsigned)items), dim3(64), 0, stream, a,
+                       mask, mask_ld);
+    return hipGetLastError();
+}
+
+const char *mask_kernel_name() { return "split_mask_kernel+split_masked_dp_kernel"; }
 
 int32_t moment_blocks(int64_t S)
 {

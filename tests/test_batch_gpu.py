@@ -56,7 +56,7 @@ def check_batch(ctx, tours, dem_np, Q, d_oracle, form="auto", xy=None, d=None, l
     return got, stats
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 def test_uneven_subset_tours(ctx, form):
     b = gen.make_batch_workload("batch-256", T=12, S=3000)
     print(f"[batch] T=12 S=3000 form={form} lengths={[len(t) for t in b.tours]}", flush=True)
@@ -101,7 +101,7 @@ def test_padded_cost_rows_and_single_tour_batch(ctx):
     assert s1.sum == sb[0].sum and s1.var == sb[0].var
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 def test_infeasible_tour_is_isolated(ctx, form):
     import paper_2511_18022_amd as sg
     w = gen.make_workload("uniform-n20", S=700)

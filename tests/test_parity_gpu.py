@@ -63,7 +63,7 @@ WORKLOADS_SMALL = ["uniform-n20", "poisson-n200"]
 
 
 @pytest.mark.parametrize("name", WORKLOADS_SMALL)
-@pytest.mark.parametrize("form", ["lane", "wave", "auto"])
+@pytest.mark.parametrize("form", ["lane", "wave", "auto", "mask"])
 def test_named_workloads_full_size(ctx, name, form):
     w = gen.make_workload(name)
     print(f"[parity] {name} S={w.S} form={form}", flush=True)
@@ -71,16 +71,17 @@ def test_named_workloads_full_size(ctx, name, form):
     check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form=form, xy=w.xy)
 
 
-def test_copula_n1000_full_size_all_scenarios(ctx):
+@pytest.mark.parametrize("form", ["auto", "mask"])
+def test_copula_n1000_full_size_all_scenarios(ctx, form):
     w = gen.make_workload("copula-n1000")
-    print(f"[parity] copula-n1000 S={w.S} form=auto (all scenarios)", flush=True)
+    print(f"[parity] copula-n1000 S={w.S} form={form} (all scenarios)", flush=True)
     d = oracle.dist_matrix(w.xy)
-    _, st = check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form="auto", xy=w.xy)
+    _, st = check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form=form, xy=w.xy)
     print(f"[parity] copula-n1000 fallback scenarios: {st.n_fallback}", flush=True)
 
 
 @pytest.mark.parametrize("S", [1, 2, 63, 64, 65, 1037, 4097])
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 def test_ragged_scenario_counts(ctx, S, form):
     w = gen.make_workload("copula-n1000", S=S)
     n = 300
@@ -109,7 +110,7 @@ def test_padded_leading_dimension(ctx):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 def test_asymmetric_user_matrix_and_subset_tour(ctx, form):
     rng = np.random.default_rng(7)
     N = 400
@@ -120,7 +121,7 @@ def test_asymmetric_user_matrix_and_subset_tour(ctx, form):
     check_against_oracle(ctx, tour, dem, 300, dmat, form=form, d=dmat)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 def test_long_zero_demand_runs_take_the_general_kernel(ctx, form):
     # windows far longer than the lane kernel's LDS history: the lane kernel must queue these
     # scenarios for the general kernel and the results must stay exact
@@ -140,7 +141,7 @@ def test_long_zero_demand_runs_take_the_general_kernel(ctx, form):
         assert st.n_fallback > 0
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 @pytest.mark.parametrize("bad", ["over_capacity", "negative"])
 def test_infeasible_demand_is_reported(ctx, form, bad):
     import paper_2511_18022_amd as sg
@@ -199,7 +200,7 @@ def test_maximum_capacity_and_run_twice_determinism(ctx):
     assert np.array_equal(c, c2)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave"])
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 @pytest.mark.parametrize("Q,lo,hi", [(16383, 4000, 16383), (16383, 1, 16383), (4681, 2000, 4681),
                                      (3000, 0, 400)])
 def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi):

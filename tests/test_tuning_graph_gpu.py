@@ -210,3 +210,14 @@ def test_graph_reports_an_infeasible_tour(sg):
     assert np.array_equal(cost[0].cpu().numpy(), oracle.split(ok_tour, d, dem, w.Q))
     g.close()
     ctx.close()
+
+
+def test_graphs_reject_the_two_kernel_ablation(sg, batch):
+    b, _, _ = batch
+    ctx = fresh_ctx(sg, b.xy)
+    ctx.set_form("mask")
+    dem = torch.from_numpy(b.demand).cuda()
+    with pytest.raises(sg.SplitError) as ei:
+        ctx.graph(max_T=2, max_total_n=2000, demand=dem, Q=b.Q)
+    assert ei.value.status == sg.SPLIT_E_INVAL
+    ctx.close()
