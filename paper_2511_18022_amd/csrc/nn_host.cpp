@@ -72,6 +72,8 @@ struct split_nn {
     int32_t cap_T = 0;
     float *partW = nullptr, *partB = nullptr;
     int64_t cap_chunks = 0;
+    float *zpart = nullptr;  // prediction: per-tile channel sums [T][tiles][128]
+    int64_t cap_zpart = 0;
     int32_t *err = nullptr;
     int32_t *h_err = nullptr;  // pinned
     // training batches
@@ -191,13 +193,27 @@ split_status check_call(split_nn *nn, const char *who, const void *tours, int32_
     return SPLIT_OK;
 }
 
-// Features, the four conv layers and the head for T tours; pred may be null.
+// Features, the four conv layers and the head for T tours. With pred (prediction) the layers
+// run fused per tile in LDS; without (training) every layer's output is kept for backward.
 split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, int32_t T,
                      int32_t n, float *pred, hipStream_t st)
 {
     split_status s = ensure_act(nn, T, n, st);
     if (s != SPLIT_OK) return s;
     NN_TRY(nn, nn_launch_features(in, tours, T, n, nn->musd, nn->Q, nn->L, nn->X, nn->err, st));
+    if (pred) {
+        const int64_t need = (int64_t)T * nn_fused_tiles(n) * kNnWidth;
+        if (need > nn->cap_zpart) {
+            NN_TRY(nn, hipDeviceSynchronize());
+            nn->cap_zpart = 0;
+            if (!realloc_dev(&nn->zpart, sizeof(float) * (size_t)need))
+                return ctx_fail(nn->ctx, SPLIT_E_NOMEM, "surrogate: pooling buffer failed");
+            nn->cap_zpart = need;
+        }
+        NN_TRY(nn, nn_launch_fwd_fused(nn->X, nn->w, nn->P, T, n, nn->zpart, nn->z, nn->a, nn->y,
+                                       pred, nn->shift, nn->scale, st));
+        return SPLIT_OK;
+    }
     NN_TRY(nn, nn_launch_conv(kNnCi0, 0, nn->X, nn->w.f[0], nn->P + nn_off_b(0), nullptr, nn->H[0],
                               T, n, st));
     for (int l = 1; l < 4; ++l)
@@ -292,7 +308,7 @@ void free_nn(split_nn *nn)
 {
     for (float *p : {nn->P, nn->m, nn->v, nn->G, nn->z, nn->a, nn->y, nn->da, nn->dz, nn->dy,
                      nn->lterms, nn->lout, nn->partW, nn->partB, nn->blabels, nn->losshist,
-                     nn->pred})
+                     nn->pred, nn->zpart})
         if (p) (void)hipFree(p);
     for (int l = 0; l < 4; ++l) {
         if (nn->w.f[l]) (void)hipFree(nn->w.f[l]);

@@ -59,6 +59,11 @@ hipError_t nn_launch_features(const NnInstance &in, const int32_t *tours, int32_
 hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *Wt,
                           const float *bias, const uint16_t *mask, uint16_t *Y, int32_t T,
                           int32_t n, hipStream_t st);
+// prediction only: the four conv layers per tile in LDS and the head (zpart [T][tiles][128])
+int32_t nn_fused_tiles(int32_t n);
+hipError_t nn_launch_fwd_fused(const uint16_t *X, const NnWeights &w, const float *P, int32_t T,
+                               int32_t n, float *zpart, float *z, float *a, float *y, float *pred,
+                               double shift, double scale, hipStream_t st);
 hipError_t nn_launch_head_fwd(const uint16_t *H4, int32_t T, int32_t n, const float *P, float *z,
                               float *a, float *y, float *pred, double shift, double scale,
                               hipStream_t st);

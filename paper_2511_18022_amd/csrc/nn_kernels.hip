@@ -248,6 +248,174 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
         }
 }
 
+// ------------------------------------------------------------------------- fused inference
+
+// All four conv layers of one tile of kFuseTP positions of one tour in LDS, for prediction only
+// (training keeps every layer's output for the backward pass). The input tile carries a halo
+// of 8 rows (2 per layer); layer l's output row r is position j0 - 6 + 2l + r, and rows at
+// positions outside the tour are set to zero, which is the zero padding of the next layer. Each
+// layer is a GEMM over 5 m-tiles of 16 rows x 128 channels: wave w owns channel tiles 2w, 2w+1
+// and reads just those weight fragments from L2, 4 K blocks ahead, so the K loop has no barrier
+// (one per layer); the activation fragments of the next K block are read from LDS while the
+// current one runs. The last layer rounds its outputs to
+// bfloat16 (as the layer-by-layer path stores them) and sums them per channel over the tile's
+// positions, in a fixed order, into zpart[t][tile][co].
+constexpr int kFuseTP = 64;
+constexpr int kFuseRows = kFuseTP + 20;     // rows of every LDS activation buffer
+constexpr int kFuseStrideX = kNnCi0 + 8;    // bf16 per input row (16 bytes of padding)
+constexpr int kFuseStrideH = kNnWidth + 8;  // bf16 per hidden row (16 bytes of padding)
+
+template <int CI, bool POOL>
+__device__ __forceinline__ void fused_layer(const uint16_t *in, uint16_t *out,
+                                            const uint16_t *Wt, const float *bias, int mtiles,
+                                            int pos0, int n, float *pool_out)
+{
+    constexpr int K = kNnTaps * CI;
+    constexpr int KB = K / 32;
+    constexpr int SIN = CI == kNnCi0 ? kFuseStrideX : kFuseStrideH;
+    constexpr int DEPTH = 4;  // weight fragments in flight (read from L2, no LDS staging)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    // this wave's two 16-channel tiles: columns (2 wave + h) * 16 + r16 of Wt[co][K]
+    const bf16x8 *w0 = reinterpret_cast<const bf16x8 *>(Wt + (long long)((2 * wave) * 16 + r16) * K +
+                                                         kq * 8);
+    const bf16x8 *w1 = w0 + (16 * K) / 8;
+    f32x4 acc[5][2];
+#pragma unroll
+    for (int mt = 0; mt < 5; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 b0[DEPTH], b1[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+        if (d < KB) {
+            b0[d] = w0[d * 4];
+            b1[d] = w1[d * 4];
+        }
+    }
+    __syncthreads();  // the input rows of this layer are in LDS
+    bf16x8 a[5], an[5];
+    auto load_a = [&](int kb, bf16x8 (&dst)[5]) {
+        const int kk = kb * 32 + kq * 8;
+        const int tap = kk / CI, ci = kk - tap * CI;
+#pragma unroll
+        for (int mt = 0; mt < 5; ++mt)
+            if (mt < mtiles)
+                dst[mt] = *reinterpret_cast<const bf16x8 *>(in + (mt * 16 + r16 + tap) * SIN + ci);
+    };
+    load_a(0, a);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        if (kb + 1 < KB) load_a(kb + 1, an);
+        const bf16x8 bb0 = b0[kb % DEPTH], bb1 = b1[kb % DEPTH];
+        if (kb + DEPTH < KB) {
+            b0[kb % DEPTH] = w0[(kb + DEPTH) * 4];
+            b1[kb % DEPTH] = w1[(kb + DEPTH) * 4];
+        }
+#pragma unroll
+        for (int mt = 0; mt < 5; ++mt) {
+            if (mt < mtiles) {
+                acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb0, acc[mt][0], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb1, acc[mt][1], 0, 0, 0);
+            }
+        }
+        if (kb + 1 < KB) {
+#pragma unroll
+            for (int mt = 0; mt < 5; ++mt) a[mt] = an[mt];
+        }
+    }
+    float sum[2] = {0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < 5; ++mt) {
+        if (mt >= mtiles) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = mt * 16 + kq * 4 + i;
+            const int pos = pos0 + row;
+            const bool inside = pos >= 0 && pos < n;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int co = (2 * wave + h) * 16 + r16;
+                float v = acc[mt][h][i] + bias[co];
+                v = v > 0.f && inside ? v : 0.f;
+                const uint16_t bv = bf16_bits_f32(v);
+                if (POOL)
+                    sum[h] += bf16_to_f32(bv);
+                else
+                    out[row * kFuseStrideH + co] = bv;
+            }
+        }
+    }
+    if (POOL) {
+        // the 4 row groups of a column, added in a fixed order
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float v = sum[h];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (kq == 0) pool_out[(2 * wave + h) * 16 + r16] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void nn_fwd_fused_kernel(const uint16_t *X, NnWeights w,
+                                                           const float *P, int32_t n,
+                                                           int32_t tiles, float *zpart)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kFuseRows * kFuseStrideX];
+    __shared__ __attribute__((aligned(16))) uint16_t ha[kFuseRows * kFuseStrideH];
+    __shared__ __attribute__((aligned(16))) uint16_t hb[kFuseRows * kFuseStrideH];
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x / tiles, k = blockIdx.x - t * tiles;
+    const int j0 = k * kFuseTP;
+    // input rows: position j0 - 8 + r (zero outside the tour), 32 channels as 4 chunks of 16 B
+    for (int e = tid; e < kFuseRows * 4; e += 256) {
+        const int r = e >> 2, c = e & 3;
+        const int pos = j0 - 8 + r;
+        u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (pos >= 0 && pos < n)
+            v = *reinterpret_cast<const u16x8 *>(X + ((long long)t * (n + 4) + pos + 2) * kNnCi0 +
+                                                c * 8);
+        *reinterpret_cast<u16x8 *>(xs + r * kFuseStrideX + c * 8) = v;
+    }
+    // layers 1..3 over 5 m-tiles (76, 72, 68 rows used), layer 4 over the tile's 64 rows
+    fused_layer<kNnCi0, false>(xs, ha, w.f[0], P + nn_off_b(0), 5, j0 - 6, n, nullptr);
+    fused_layer<kNnWidth, false>(ha, hb, w.f[1], P + nn_off_b(1), 5, j0 - 4, n, nullptr);
+    fused_layer<kNnWidth, false>(hb, ha, w.f[2], P + nn_off_b(2), 5, j0 - 2, n, nullptr);
+    fused_layer<kNnWidth, true>(ha, nullptr, w.f[3], P + nn_off_b(3), 4, j0, n,
+                                zpart + ((long long)t * tiles + k) * kNnWidth);
+}
+
+// Head from the per-tile sums: z[c] = (sum over tiles, in order) / n, then as nn_head_fwd_kernel.
+__global__ __launch_bounds__(128) void nn_head_pool_kernel(const float *zpart, int32_t tiles,
+                                                           int32_t n, const float *P, float *z,
+                                                           float *a, float *y, float *pred,
+                                                           double shift, double scale)
+{
+    __shared__ float zs[kNnWidth];
+    __shared__ float red[kNnWidth];
+    const int t = blockIdx.x, c = threadIdx.x;
+    float sum = 0.f;
+    for (int k = 0; k < tiles; ++k) sum += zpart[((long long)t * tiles + k) * kNnWidth + c];
+    const float zc = sum / (float)n;
+    zs[c] = zc;
+    z[(long long)t * kNnWidth + c] = zc;
+    __syncthreads();
+    const float *Wa = P + kNnOffWa;
+    float acc = P[kNnOffBa + c];
+    for (int i = 0; i < kNnWidth; ++i) acc += Wa[c * kNnWidth + i] * zs[i];
+    a[(long long)t * kNnWidth + c] = acc;
+    red[c] = P[kNnOffWb + c] * (acc > 0.f ? acc : 0.f);
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if (c < off) red[c] += red[c + off];
+        __syncthreads();
+    }
+    if (c == 0) {
+        const float yt = red[0] + P[kNnOffBb];
+        y[t] = yt;
+        if (pred) pred[t] = (float)((double)yt * scale + shift);
+    }
+}
+
 // ------------------------------------------------------------------------- pool and head
 
 // One workgroup of 256 threads per tour: z = mean over positions of H4, a = Wa z + ba,
@@ -709,6 +877,22 @@ hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *W
         hipLaunchKernelGGL((nn_conv_kernel<kNnWidth, 1>), g, b, 0, st, X, Wt, bias, mask, Y, T, n);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int32_t nn_fused_tiles(int32_t n) { return (n + kFuseTP - 1) / kFuseTP; }
+
+hipError_t nn_launch_fwd_fused(const uint16_t *X, const NnWeights &w, const float *P, int32_t T,
+                               int32_t n, float *zpart, float *z, float *a, float *y, float *pred,
+                               double shift, double scale, hipStream_t st)
+{
+    const int32_t tiles = nn_fused_tiles(n);
+    hipLaunchKernelGGL(nn_fwd_fused_kernel, dim3((unsigned)((long long)T * tiles)), dim3(256), 0,
+                       st, X, w, P, n, tiles, zpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nn_head_pool_kernel, dim3(T), dim3(128), 0, st, zpart, tiles, n, P, z, a, y,
+                       pred, shift, scale);
     return hipGetLastError();
 }
 

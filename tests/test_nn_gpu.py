@@ -264,3 +264,28 @@ def test_bad_tour_ids_are_rejected(sg, env):
         net.predict(torch.from_numpy(bad).cuda())
     assert ei.value.status == sg.SPLIT_E_TOUR
     net.close()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 130, 200])
+def test_fused_prediction_across_tile_boundaries(sg, n):
+    # prediction runs the four layers per 64-position tile in LDS with an 8-row halo; tours
+    # shorter than, equal to and straddling tiles must give the layer-by-layer reference
+    Nn = 200
+    xy = gen.coords(52, Nn)
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(xy)
+    dem = gen.demand_uniform(52, Nn, 256, 0, 30)
+    net = sg.SplitNN(ctx, seed=6, length_scale=L)
+    net.set_scenarios(torch.from_numpy(dem).cuda(), Q)
+    net.set_norm(0.0, 1.0)
+    q = positive_params(n + 1)
+    net.set_params(q)
+    tours = np.stack([gen.tour(52, Nn, n, variant=v) for v in range(1, 4)])
+    d = oracle.dist_matrix(xy)
+    Xs = [nnref.features(t, d, *nnref.demand_stats(dem), Q, L, xy=xy) for t in tours]
+    y = net.predict(torch.from_numpy(tours).cuda()).cpu().numpy()
+    y_ref = nnref.forward(q.astype(np.float64), Xs, bf16=True)
+    print(f"[nn] fused n={n}: max err {np.abs(y - y_ref).max():.3e}", flush=True)
+    assert np.all(np.abs(y - y_ref) <= 2e-5 * (1 + np.abs(y_ref)))
+    net.close()
+    ctx.close()
