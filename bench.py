@@ -43,9 +43,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+LANE_BEGIN = b"// ------------------------------------------------------------------------- lane kernel"
+LANE_END = b"// ------------------------------------------------------------------------- wave kernel"
+INTERNAL_H = os.path.join(ROOT, "paper_2511_18022_amd", "csrc", "split_internal.h")
+
+
 def kernel_source_sha() -> str:
+    """Hash of the lane kernel's source: its section of the kernel file and the shared internal
+    header (other kernels in the file do not change it)."""
     with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+        src = fh.read()
+    i, j = src.index(LANE_BEGIN), src.index(LANE_END)
+    with open(INTERNAL_H, "rb") as fh:
+        hdr = fh.read()
+    return hashlib.sha256(src[i:j] + hdr).hexdigest()[:16]
 
 
 def measured_traffic(workload: str, launch_scenarios: int):
@@ -405,9 +416,9 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the scenario shards and the one 24-byte all-reduce of a multi-GPU run are "
-              "described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported (a multi-GPU "
+              "run would shard the scenarios and all-reduce 24 bytes of moments; it is not "
+              "built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

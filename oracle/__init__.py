@@ -3,7 +3,7 @@
 Plain, slow and obviously correct: ``oracle.c`` follows the paper's Eq. (1) (Section 3)
 scenario by scenario, plus Eq. (2) masks and Eq. (3) as a cross-check, exact rounded
 Euclidean distances and exact sample-average moments. Only ``tests/``,
-``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg may import this package.
+the smoke check and the benchmark's CPU-baseline leg may import this package.
 It imports nothing from the GPU library, and the GPU library imports nothing from it.
 """
 from __future__ import annotations
