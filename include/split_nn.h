@@ -114,6 +114,14 @@ split_status split_topk_smallest(split_ctx *ctx, const float *scores, int64_t C,
                                  int32_t *idx, void *hip_stream);
 
 /*
+ * Predict T tours (DEVICE int32 [T][n]) and write the indices of the K lowest predictions to
+ * idx (DEVICE int32 [K], increasing; ties to the lower index), using the surrogate's own
+ * scratch. pred DEVICE fp32 [T] or NULL (then internal). Blocks. 1 <= K <= T.
+ */
+split_status split_nn_shortlist(split_nn *nn, const int32_t *tours, int32_t T, int32_t n,
+                                int32_t K, int32_t *idx, float *pred, void *hip_stream);
+
+/*
  * Screening: predict the C candidate tours (DEVICE int32 [C][n]), keep the K with the lowest
  * prediction, evaluate those exactly with split_eval_batch against demand (DEVICE int16
  * [N][ld], S scenarios, capacity Q), and return the best by exact mean.

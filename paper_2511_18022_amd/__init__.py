@@ -32,7 +32,7 @@ EXPORTED = [
     "split_nn_create", "split_nn_destroy", "split_nn_params_get", "split_nn_params_set",
     "split_nn_set_norm", "split_nn_set_scenarios", "split_nn_predict", "split_nn_gradient",
     "split_nn_train_step", "split_nn_train", "split_nn_step", "split_nn_save", "split_nn_load",
-    "split_topk_smallest", "split_nn_screen",
+    "split_topk_smallest", "split_nn_shortlist", "split_nn_screen",
     # include/split_search.h
     "split_search",
 ]
@@ -145,6 +145,7 @@ def load_library(path: str = LIB_PATH):
     lib.split_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.split_nn_load.argtypes = [P, ctypes.c_char_p]
     lib.split_topk_smallest.argtypes = [P, P, i64, i64, P, P]
+    lib.split_nn_shortlist.argtypes = [P, P, i32, i32, i32, P, P, P]
     lib.split_search.argtypes = [P, P, P, i32, P, i64, i64, i32, i32, i32, f64, i64, u64, P, P,
                                  P, i32, P, P, P]
     lib.split_nn_screen.argtypes = [P, P, i64, i32, i64, P, i64, i64, i32, P, P, P,
@@ -569,6 +570,20 @@ class SplitNN:
 
     def load(self, path: str):
         self._check(self._lib.split_nn_load(self._h, os.fsencode(path)))
+
+    def shortlist(self, tours, K: int, pred=None, stream=None):
+        """Indices (CUDA int32 [K], increasing) of the K tours with the lowest predictions."""
+        import torch
+        T, n = _cuda_i32_matrix(tours)
+        idx = torch.empty(int(K), dtype=torch.int32, device=tours.device)
+        if pred is not None:
+            _cuda_f32_vector(pred, T, "pred")
+        self._check(self._lib.split_nn_shortlist(
+            self._h, ctypes.c_void_p(tours.data_ptr()), T, n, int(K),
+            ctypes.c_void_p(idx.data_ptr()),
+            ctypes.c_void_p(pred.data_ptr()) if pred is not None else None,
+            self._stream(stream, tours.device)))
+        return idx
 
     def screen(self, cands, K: int, demand, Q: int, S: int | None = None, pred=None,
                stream=None):

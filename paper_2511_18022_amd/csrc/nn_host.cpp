@@ -715,6 +715,38 @@ split_status split_topk_smallest(split_ctx *ctx, const float *scores, int64_t C,
     return s;
 }
 
+split_status split_nn_shortlist(split_nn *nn, const int32_t *tours, int32_t T, int32_t n,
+                                int32_t K, int32_t *idx, float *pred, void *hip_stream)
+{
+    if (!nn) return SPLIT_E_INVAL;
+    if (!idx || K < 1 || K > T)
+        return ctx_fail(nn->ctx, SPLIT_E_INVAL, "split_nn_shortlist: need idx and 1 <= K <= T");
+    NnInstance in;
+    split_status s = check_call(nn, "split_nn_shortlist", tours, T, n, &in);
+    if (s != SPLIT_OK) return s;
+    Guard g(nn->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    float *pr = pred;
+    if (!pr) {
+        if (T > nn->cap_pred) {
+            NN_TRY(nn, hipDeviceSynchronize());
+            if (!realloc_dev(&nn->pred, sizeof(float) * (size_t)T))
+                return ctx_fail(nn->ctx, SPLIT_E_NOMEM, "split_nn_shortlist: prediction buffer");
+            nn->cap_pred = T;
+        }
+        pr = nn->pred;
+    }
+    NN_TRY(nn, hipMemsetAsync(nn->err, 0, sizeof(int32_t), st));
+    for (int32_t t0 = 0; t0 < T; t0 += kPredChunk) {
+        const int32_t Tc = T - t0 < kPredChunk ? T - t0 : kPredChunk;
+        s = forward(nn, in, tours + (int64_t)t0 * n, Tc, n, pr + t0, st);
+        if (s != SPLIT_OK) return s;
+    }
+    s = check_ids(nn, "split_nn_shortlist", st);
+    if (s != SPLIT_OK) return s;
+    return topk_run(nn->ctx, nn->tk, pr, T, K, idx, st);
+}
+
 split_status split_nn_screen(split_nn *nn, const int32_t *cands, int64_t C, int32_t n, int64_t K,
                              const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
                              float *pred, int32_t *short_idx, double *short_mean,

@@ -80,6 +80,9 @@ hipError_t nn_launch_pack(const float *P, const NnWeights &w, hipStream_t st);
 hipError_t nn_launch_gather(const int32_t *src, const float *lab, const int32_t *idx, int32_t B,
                             int32_t n, int32_t *dst, float *dlab, hipStream_t st);
 hipError_t nn_launch_loss(const float *terms, int32_t T, float *out, hipStream_t st);
+// candidates [count][n] from cur [n] and moves [count][3] = (type, i, j), validated by the caller
+hipError_t nn_launch_moves(const int32_t *cur, const int32_t *moves, int32_t count, int32_t n,
+                           int32_t *out, hipStream_t st);
 hipError_t nn_launch_check_ids(const int32_t *ids, long long count, int32_t N, int32_t *err,
                                hipStream_t st);
 hipError_t nn_launch_topk(const float *s, long long C, long long K, NnSelect *sel,

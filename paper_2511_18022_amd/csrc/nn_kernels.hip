@@ -813,6 +813,31 @@ __global__ __launch_bounds__(256) void nn_check_ids_kernel(const int32_t *ids, l
     }
 }
 
+// Candidate tours from one tour and a list of moves, one workgroup per candidate:
+// move (0, i, j) reverses positions min(i,j)..max(i,j); move (1, i, j) moves the customer at
+// position i to position j. Each output position gathers its customer from the input tour.
+__global__ __launch_bounds__(256) void nn_moves_kernel(const int32_t *cur, const int32_t *moves,
+                                                       int32_t n, int32_t *out)
+{
+    const long long c = blockIdx.x;
+    const int type = moves[3 * c], i = moves[3 * c + 1], j = moves[3 * c + 2];
+    int32_t *dst = out + c * n;
+    for (int p = threadIdx.x; p < n; p += 256) {
+        int src = p;
+        if (type == 0) {
+            const int lo = i < j ? i : j, hi = i < j ? j : i;
+            if (p >= lo && p <= hi) src = lo + hi - p;
+        } else if (i < j) {
+            if (p >= i && p < j) src = p + 1;
+            else if (p == j) src = i;
+        } else {
+            if (p > j && p <= i) src = p - 1;
+            else if (p == j) src = i;
+        }
+        dst[p] = cur[src];
+    }
+}
+
 // out[0] = (sum of terms[0..T-1], in order) / T
 __global__ void nn_loss_kernel(const float *terms, int32_t T, float *out)
 {
@@ -837,6 +862,14 @@ hipError_t nn_launch_check_ids(const int32_t *ids, long long count, int32_t N, i
     const long long g = (count + 255) / 256;
     hipLaunchKernelGGL(nn_check_ids_kernel, dim3((unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096)),
                        dim3(256), 0, st, ids, count, N, err);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_moves(const int32_t *cur, const int32_t *moves, int32_t count, int32_t n,
+                           int32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_moves_kernel, dim3((unsigned)count), dim3(256), 0, st, cur, moves, n,
+                       out);
     return hipGetLastError();
 }
 

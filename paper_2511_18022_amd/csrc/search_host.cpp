@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/split_search.h"
+#include "nn_internal.h"
 #include "split_internal.h"
 
 using namespace splitgpu;
@@ -23,15 +24,25 @@ uint64_t next_u64(uint64_t &s)
     return z ^ (z >> 31);
 }
 
-// One random neighbour of cur (n >= 2) written to out: a 2-opt or a relocate move, i != j.
-void neighbour(const int32_t *cur, int32_t n, uint64_t &rs, int32_t *out)
+// One random move for a tour of n >= 2 positions: (0, i, j) a 2-opt reversal of positions
+// min(i,j)..max(i,j), (1, i, j) a relocation of the customer at i to position j; i != j.
+void draw_move(int32_t n, uint64_t &rs, int32_t *mv)
 {
-    memcpy(out, cur, sizeof(int32_t) * (size_t)n);
     const uint64_t r = next_u64(rs);
     const int32_t i = (int32_t)((r & 0xFFFFFFFFull) % (uint64_t)n);
     int32_t j = (int32_t)((r >> 32) % (uint64_t)(n - 1));
     if (j >= i) ++j;
-    if (next_u64(rs) & 1) {
+    mv[0] = (next_u64(rs) & 1) ? 0 : 1;
+    mv[1] = i;
+    mv[2] = j;
+}
+
+// cur with move mv applied, written to out (the host twin of the device move kernel)
+void apply_move(const int32_t *cur, int32_t n, const int32_t *mv, int32_t *out)
+{
+    memcpy(out, cur, sizeof(int32_t) * (size_t)n);
+    const int32_t i = mv[1], j = mv[2];
+    if (mv[0] == 0) {
         // 2-opt: reverse positions lo..hi
         int32_t lo = i < j ? i : j, hi = i < j ? j : i;
         for (; lo < hi; ++lo, --hi) {
@@ -51,16 +62,14 @@ void neighbour(const int32_t *cur, int32_t n, uint64_t &rs, int32_t *out)
 }
 
 struct SearchBuffers {
-    int32_t *cost = nullptr, *dcand = nullptr, *didx = nullptr;
-    float *dpred = nullptr;
+    int32_t *cost = nullptr, *dcand = nullptr, *didx = nullptr, *dcur = nullptr;
+    int32_t *dmoves = nullptr, *dsel = nullptr;
     split_graph *graph = nullptr;
     ~SearchBuffers()
     {
         split_graph_destroy(graph);
-        if (cost) (void)hipFree(cost);
-        if (dcand) (void)hipFree(dcand);
-        if (didx) (void)hipFree(didx);
-        if (dpred) (void)hipFree(dpred);
+        for (int32_t *p : {cost, dcand, didx, dcur, dmoves, dsel})
+            if (p) (void)hipFree(p);
     }
 };
 
@@ -115,15 +124,17 @@ extern "C" split_status split_search(split_ctx *ctx, split_nn *nn, const int32_t
     if (hipMalloc(&b.cost, sizeof(int32_t) * (size_t)batch * (size_t)S) != hipSuccess)
         return ctx_fail(ctx, SPLIT_E_NOMEM, "split_search: cost buffer");
     if (nn && (hipMalloc(&b.dcand, sizeof(int32_t) * (size_t)pool * n) != hipSuccess ||
-               hipMalloc(&b.dpred, sizeof(float) * (size_t)pool) != hipSuccess ||
-               hipMalloc(&b.didx, sizeof(int32_t) * (size_t)batch) != hipSuccess))
+               hipMalloc(&b.didx, sizeof(int32_t) * (size_t)batch) != hipSuccess ||
+               hipMalloc(&b.dcur, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+               hipMalloc(&b.dmoves, sizeof(int32_t) * 3 * (size_t)pool) != hipSuccess ||
+               hipMalloc(&b.dsel, sizeof(int32_t) * (size_t)batch * n) != hipSuccess))
         return ctx_fail(ctx, SPLIT_E_NOMEM, "split_search: surrogate buffers");
     split_status s = split_graph_create(ctx, batch, (int64_t)batch * n, demand, S, ld, Q, b.cost, S,
                                         &b.graph);
     if (s != SPLIT_OK) return s;
 
-    std::vector<int32_t> cur(tour0, tour0 + n), cand((size_t)pool * n), sel((size_t)batch * n);
-    std::vector<int32_t> hidx((size_t)batch);
+    std::vector<int32_t> cur(tour0, tour0 + n), sel((size_t)batch * n);
+    std::vector<int32_t> moves(3 * (size_t)pool);
     std::vector<int64_t> ptr((size_t)batch + 1);
     std::vector<split_stats> stats((size_t)batch);
     std::vector<int32_t> status((size_t)batch);
@@ -148,25 +159,30 @@ extern "C" split_status split_search(split_ctx *ctx, split_nn *nn, const int32_t
     for (int32_t t = 0; t <= batch; ++t) ptr[t] = (int64_t)t * n;
     uint64_t rs = seed;
     while (n >= 2 && res.iterations < max_iters && elapsed() < budget_s) {
-        for (int32_t c = 0; c < pool; ++c) neighbour(cur.data(), n, rs, cand.data() + (size_t)c * n);
-        const int32_t *eval = cand.data();
+        for (int32_t c = 0; c < pool; ++c) draw_move(n, rs, moves.data() + 3 * (size_t)c);
         if (nn) {
-            if (hipMemcpyAsync(b.dcand, cand.data(), sizeof(int32_t) * (size_t)pool * n,
-                               hipMemcpyHostToDevice, st) != hipSuccess)
-                return ctx_fail(ctx, SPLIT_E_HIP, "split_search: candidate upload failed");
-            s = split_nn_predict(nn, b.dcand, pool, n, b.dpred, hip_stream);
-            if (s == SPLIT_OK) s = split_topk_smallest(ctx, b.dpred, pool, batch, b.didx, hip_stream);
+            // candidates built on the device from the incumbent and the moves, predicted, and
+            // the shortlist gathered there; only the batch comes back for exact evaluation
+            if (hipMemcpyAsync(b.dcur, cur.data(), sizeof(int32_t) * (size_t)n,
+                               hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(b.dmoves, moves.data(), sizeof(int32_t) * 3 * (size_t)pool,
+                               hipMemcpyHostToDevice, st) != hipSuccess ||
+                nn_launch_moves(b.dcur, b.dmoves, pool, n, b.dcand, st) != hipSuccess)
+                return ctx_fail(ctx, SPLIT_E_HIP, "split_search: building the candidates failed");
+            s = split_nn_shortlist(nn, b.dcand, pool, n, batch, b.didx, nullptr, hip_stream);
             if (s != SPLIT_OK) return s;
-            if (hipMemcpyAsync(hidx.data(), b.didx, sizeof(int32_t) * (size_t)batch,
+            if (nn_launch_gather(b.dcand, nullptr, b.didx, batch, n, b.dsel, nullptr, st) !=
+                    hipSuccess ||
+                hipMemcpyAsync(sel.data(), b.dsel, sizeof(int32_t) * (size_t)batch * n,
                                hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return ctx_fail(ctx, SPLIT_E_HIP, "split_search: shortlist copy failed");
-            for (int32_t k = 0; k < batch; ++k)
-                memcpy(sel.data() + (size_t)k * n, cand.data() + (size_t)hidx[k] * n,
-                       sizeof(int32_t) * (size_t)n);
-            eval = sel.data();
             res.predicted += pool;
+        } else {
+            for (int32_t c = 0; c < batch; ++c)
+                apply_move(cur.data(), n, moves.data() + 3 * (size_t)c, sel.data() + (size_t)c * n);
         }
+        const int32_t *eval = sel.data();
         s = split_graph_launch(b.graph, eval, ptr.data(), batch, st);
         if (s == SPLIT_OK) s = split_graph_stats(b.graph, stats.data(), status.data());
         if (s != SPLIT_OK) return s;

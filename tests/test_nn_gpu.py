@@ -289,3 +289,13 @@ def test_fused_prediction_across_tile_boundaries(sg, n):
     assert np.all(np.abs(y - y_ref) <= 2e-5 * (1 + np.abs(y_ref)))
     net.close()
     ctx.close()
+
+
+def test_shortlist_is_topk_of_predict(sg, env):
+    net = make_net(sg, env, seed=2)
+    cands = np.stack([gen.tour(45, N, NL, variant=v) for v in range(1, 301)])
+    dc = torch.from_numpy(cands).cuda()
+    pred = net.predict(dc).cpu().numpy()
+    idx = net.shortlist(dc, 37).cpu().numpy()
+    assert np.array_equal(idx, np.sort(np.lexsort((np.arange(len(pred)), pred))[:37]))
+    net.close()
