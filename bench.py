@@ -59,6 +59,33 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(src[i:j] + hdr).hexdigest()[:16]
 
 
+NN_SRC = os.path.join(ROOT, "paper_2511_18022_amd", "csrc", "nn_kernels.hip")
+NN_H = os.path.join(ROOT, "paper_2511_18022_amd", "csrc", "nn_internal.h")
+
+
+def nn_source_sha() -> str:
+    """Hash of the surrogate's kernel file and its internal header (the fused prediction kernel
+    and the packing of its fragment-ordered weights)."""
+    h = hashlib.sha256()
+    for path in (NN_SRC, NN_H):
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_nn_traffic(n: int):
+    """HBM bytes per predicted tour of the fused prediction kernel from committed rocprofv3
+    counter runs, if they match this source and tour length."""
+    try:
+        with open(os.path.join(PROFILES, "traffic_nn_fwd_fused_kernel_screen.json")) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != nn_source_sha() or t.get("n") != n:
+        return None
+    return t.get("bytes_per_tour")
+
+
 def measured_traffic(workload: str, launch_scenarios: int):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
     path = os.path.join(PROFILES, f"traffic_split_lane_kernel_{workload}.json")
@@ -222,11 +249,15 @@ def run_screen(args, threads):
     screen_s = time.perf_counter() - t0
     # forward pass alone (HIP events on its stream): the conv layers' MFMA rate
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.timing(True)
+    net.timing_reset()
     e0.record()
     net.predict(ca, out=res["pred"])
     e1.record()
     torch.cuda.synchronize()
     predict_ms = e0.elapsed_time(e1)
+    fused_ms, fused_launches = net.timing_get()
+    net.timing(False)
     # exact-only, timed
     t0 = time.perf_counter()
     means = exact_means(ctx, w.cands, dem, w.Q)
@@ -241,7 +272,12 @@ def run_screen(args, threads):
         f"predicted rank {rank_of_best}, Spearman {rank_corr:.4f}")
     n = w.N
     flops_per_tour = 2.0 * n * 128 * (5 * 8 + 3 * 5 * 128)
-    achieved = flops_per_tour * C / (predict_ms * 1e-3) / 1e12
+    # the dominant kernel: the fused convolution kernel, HIP-event timed per launch; a launch
+    # is one forward pass of up to 1024 tours
+    per_launch = C / fused_launches
+    # HBM bytes per launch from the committed counter runs (same source and tour length)
+    traffic_per_tour = measured_nn_traffic(int(ca.shape[1]))
+    achieved = flops_per_tour * per_launch / (fused_ms / fused_launches * 1e-3) / 1e12
     out = {
         "metric": METRIC_SCREEN,
         "value": C / screen_s,
@@ -267,8 +303,12 @@ def run_screen(args, threads):
                    "candidates_recipe": "2-opt base tour with 1..60 random segment reversals"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "surrogate forward (nn_conv_kernel x4 + head)",
-                     "kernel_avg_ms": predict_ms, "flops_per_tour": flops_per_tour},
+                     "traffic": (None if traffic_per_tour is None
+                                 else traffic_per_tour * per_launch),
+                     "kernel": "nn_fwd_fused_kernel",
+                     "kernel_avg_ms": fused_ms / fused_launches, "launches": fused_launches,
+                     "tours_per_launch": per_launch, "flops_per_tour": flops_per_tour,
+                     "predict_ms_all_kernels": predict_ms},
     }
     if not args.no_cpu_baseline:
         import oracle

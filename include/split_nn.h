@@ -137,6 +137,16 @@ split_status split_nn_screen(split_nn *nn, const int32_t *cands, int64_t C, int3
                              float *pred, int32_t *short_idx, double *short_mean,
                              int64_t *best_idx, double *best_mean, void *hip_stream);
 
+/*
+ * Kernel timing for benchmarks: when enabled, every prediction records HIP events on the
+ * caller's stream around the fused convolution kernel (the four conv layers and the pooling,
+ * one launch per forward pass of up to 1024 tours). split_nn_timing_get waits for the recorded
+ * launches and returns their accumulated milliseconds and count since the last reset.
+ */
+split_status split_nn_timing_enable(split_nn *nn, int enable);
+split_status split_nn_timing_get(split_nn *nn, double *ms_total, int64_t *launches);
+split_status split_nn_timing_reset(split_nn *nn);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,8 +12,9 @@
  * positions i..j -- or a relocate move -- take the customer at position i out and insert it at
  * position j -- with equal probability, i != j uniform, from a splitmix64 stream of `seed`).
  * Without a surrogate (nn == NULL) pool must equal batch and all of them are evaluated exactly.
- * With a surrogate the pool is predicted and the `batch` lowest predictions are evaluated
- * exactly (split_nn_predict, split_topk_smallest). Exact evaluation replays a captured graph
+ * With a surrogate the pool is built on the device from the incumbent and the moves, predicted,
+ * and the `batch` lowest predictions are evaluated exactly (split_nn_shortlist; ties go to the
+ * earlier drawn move). Exact evaluation replays a captured graph
  * (split_graph_*). The incumbent moves to the best evaluated neighbour when its exact mean is
  * lower. The loop stops when budget_s seconds of wall-clock time have passed (checked after
  * every iteration) or after max_iters iterations.

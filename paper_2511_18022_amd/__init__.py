@@ -32,7 +32,8 @@ EXPORTED = [
     "split_nn_create", "split_nn_destroy", "split_nn_params_get", "split_nn_params_set",
     "split_nn_set_norm", "split_nn_set_scenarios", "split_nn_predict", "split_nn_gradient",
     "split_nn_train_step", "split_nn_train", "split_nn_step", "split_nn_save", "split_nn_load",
-    "split_topk_smallest", "split_nn_shortlist", "split_nn_screen",
+    "split_topk_smallest", "split_nn_shortlist", "split_nn_screen", "split_nn_timing_enable",
+    "split_nn_timing_get", "split_nn_timing_reset",
     # include/split_search.h
     "split_search",
 ]
@@ -146,6 +147,9 @@ def load_library(path: str = LIB_PATH):
     lib.split_nn_load.argtypes = [P, ctypes.c_char_p]
     lib.split_topk_smallest.argtypes = [P, P, i64, i64, P, P]
     lib.split_nn_shortlist.argtypes = [P, P, i32, i32, i32, P, P, P]
+    lib.split_nn_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.split_nn_timing_get.argtypes = [P, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    lib.split_nn_timing_reset.argtypes = [P]
     lib.split_search.argtypes = [P, P, P, i32, P, i64, i64, i32, i32, i32, f64, i64, u64, P, P,
                                  P, i32, P, P, P]
     lib.split_nn_screen.argtypes = [P, P, i64, i32, i64, P, i64, i64, i32, P, P, P,
@@ -564,6 +568,19 @@ class SplitNN:
         s = ctypes.c_int64()
         self._check(self._lib.split_nn_step(self._h, ctypes.byref(s)))
         return int(s.value)
+
+    def timing(self, enable: bool = True):
+        """Time the fused convolution kernel of every prediction with HIP events."""
+        self._check(self._lib.split_nn_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_reset(self):
+        self._check(self._lib.split_nn_timing_reset(self._h))
+
+    def timing_get(self):
+        """(milliseconds, launches) of the timed fused-kernel launches since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self._lib.split_nn_timing_get(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
 
     def save(self, path: str):
         self._check(self._lib.split_nn_save(self._h, os.fsencode(path)))

@@ -89,6 +89,12 @@ struct split_nn {
     int64_t cap_sidx = 0, cap_stours = 0;
     int32_t *ecost = nullptr;
     int64_t cap_ecost = 0;
+    // timing of the fused prediction kernel
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tpairs;
+    size_t tpairs_used = 0;
+    double ms_acc = 0.0;
+    int64_t launches = 0;
 };
 
 namespace {
@@ -195,6 +201,46 @@ split_status check_call(split_nn *nn, const char *who, const void *tours, int32_
 
 // Features, the four conv layers and the head for T tours. With pred (prediction) the layers
 // run fused per tile in LDS; without (training) every layer's output is kept for backward.
+constexpr size_t kMaxTimingPairs = 4096;
+
+split_status collect_timing(split_nn *nn)
+{
+    for (size_t k = 0; k < nn->tpairs_used; ++k) {
+        NN_TRY(nn, hipEventSynchronize(nn->tpairs[k].second));
+        float ms = 0.f;
+        NN_TRY(nn, hipEventElapsedTime(&ms, nn->tpairs[k].first, nn->tpairs[k].second));
+        nn->ms_acc += ms;
+        nn->launches += 1;
+    }
+    nn->tpairs_used = 0;
+    return SPLIT_OK;
+}
+
+// Records the start event of a timed launch on st and hands back its stop event (nullptr when
+// timing is off).
+split_status timing_begin(split_nn *nn, hipStream_t st, hipEvent_t *stop)
+{
+    *stop = nullptr;
+    if (!nn->timing) return SPLIT_OK;
+    if (nn->tpairs_used == kMaxTimingPairs) {
+        split_status s = collect_timing(nn);
+        if (s != SPLIT_OK) return s;
+    }
+    if (nn->tpairs_used == nn->tpairs.size()) {
+        hipEvent_t a, b;
+        NN_TRY(nn, hipEventCreate(&a));
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return ctx_fail(nn->ctx, SPLIT_E_HIP, "surrogate: timing event failed");
+        }
+        nn->tpairs.emplace_back(a, b);
+    }
+    auto &pr = nn->tpairs[nn->tpairs_used++];
+    NN_TRY(nn, hipEventRecord(pr.first, st));
+    *stop = pr.second;
+    return SPLIT_OK;
+}
+
 split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, int32_t T,
                      int32_t n, float *pred, hipStream_t st)
 {
@@ -210,8 +256,13 @@ split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, i
                 return ctx_fail(nn->ctx, SPLIT_E_NOMEM, "surrogate: pooling buffer failed");
             nn->cap_zpart = need;
         }
-        NN_TRY(nn, nn_launch_fwd_fused(nn->X, nn->w, nn->P, T, n, nn->zpart, nn->z, nn->a, nn->y,
-                                       pred, nn->shift, nn->scale, st));
+        hipEvent_t stop = nullptr;
+        s = timing_begin(nn, st, &stop);
+        if (s != SPLIT_OK) return s;
+        NN_TRY(nn, nn_launch_fwd_fused(nn->X, nn->w, nn->P, T, n, nn->zpart, st));
+        if (stop) NN_TRY(nn, hipEventRecord(stop, st));
+        NN_TRY(nn, nn_launch_head_pool(nn->zpart, T, n, nn->P, nn->z, nn->a, nn->y, pred,
+                                       nn->shift, nn->scale, st));
         return SPLIT_OK;
     }
     NN_TRY(nn, nn_launch_conv(kNnCi0, 0, nn->X, nn->w.f[0], nn->P + nn_off_b(0), nullptr, nn->H[0],
@@ -313,6 +364,7 @@ void free_nn(split_nn *nn)
     for (int l = 0; l < 4; ++l) {
         if (nn->w.f[l]) (void)hipFree(nn->w.f[l]);
         if (nn->w.b[l]) (void)hipFree(nn->w.b[l]);
+        if (nn->w.g[l]) (void)hipFree(nn->w.g[l]);
         if (nn->H[l]) (void)hipFree(nn->H[l]);
     }
     for (uint16_t *p : {nn->X, nn->dP[0], nn->dP[1]})
@@ -322,6 +374,11 @@ void free_nn(split_nn *nn)
     if (nn->musd) (void)hipFree(nn->musd);
     if (nn->h_err) (void)hipHostFree(nn->h_err);
     free_topk(nn->tk);
+    for (auto &pr : nn->tpairs) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    nn->tpairs.clear();
 }
 
 // He-uniform weights from the seed, zero biases.
@@ -383,10 +440,12 @@ split_status split_nn_create(split_ctx *ctx, uint64_t seed, double length_scale,
     bool ok = g.ok;
     for (float **p : {&nn->P, &nn->m, &nn->v, &nn->G})
         ok = ok && hipMalloc(p, sizeof(float) * kNnParams) == hipSuccess;
-    ok = ok && hipMalloc(&nn->w.f[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess;
+    ok = ok && hipMalloc(&nn->w.f[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess &&
+         hipMalloc(&nn->w.g[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess;
     for (int l = 1; l < 4; ++l)
         ok = ok && hipMalloc(&nn->w.f[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess &&
-             hipMalloc(&nn->w.b[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess;
+             hipMalloc(&nn->w.b[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess &&
+             hipMalloc(&nn->w.g[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess;
     ok = ok && hipMalloc(&nn->err, sizeof(int32_t)) == hipSuccess &&
          hipMalloc(&nn->lout, sizeof(float)) == hipSuccess &&
          hipHostMalloc((void **)&nn->h_err, sizeof(int32_t), 0) == hipSuccess;
@@ -826,6 +885,34 @@ split_status split_nn_screen(split_nn *nn, const int32_t *cands, int64_t C, int3
     *best_idx = bi;
     *best_mean = bm;
     return SPLIT_OK;
+}
+
+split_status split_nn_timing_enable(split_nn *nn, int enable)
+{
+    if (!nn) return SPLIT_E_INVAL;
+    nn->timing = enable != 0;
+    return SPLIT_OK;
+}
+
+split_status split_nn_timing_get(split_nn *nn, double *ms_total, int64_t *launches)
+{
+    if (!nn) return SPLIT_E_INVAL;
+    Guard g(nn->device);
+    split_status s = collect_timing(nn);
+    if (s != SPLIT_OK) return s;
+    if (ms_total) *ms_total = nn->ms_acc;
+    if (launches) *launches = nn->launches;
+    return SPLIT_OK;
+}
+
+split_status split_nn_timing_reset(split_nn *nn)
+{
+    if (!nn) return SPLIT_E_INVAL;
+    Guard g(nn->device);
+    split_status s = collect_timing(nn);
+    nn->ms_acc = 0.0;
+    nn->launches = 0;
+    return s;
 }
 
 }  // extern "C"

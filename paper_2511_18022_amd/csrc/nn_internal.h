@@ -40,8 +40,9 @@ struct NnInstance {
 // bf16 weight copies: f[l] = forward layout [co][tap * CI + ci]; b[l] (l >= 1) = backward-data
 // layout [ci][tap' * 128 + co] with tap' = 4 - tap.
 struct NnWeights {
-    uint16_t *f[4];
-    uint16_t *b[4];
+    uint16_t *f[4];  // layer l: bf16 [co][tap * CI + ci]
+    uint16_t *b[4];  // layers 1..3: the flipped, transposed taps for the data gradient
+    uint16_t *g[4];  // layer l in MFMA fragment order (the fused prediction kernel's reads)
 };
 
 // Radix-select state: the key prefix found so far, its mask, and the rank still to reach.
@@ -59,11 +60,14 @@ hipError_t nn_launch_features(const NnInstance &in, const int32_t *tours, int32_
 hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *Wt,
                           const float *bias, const uint16_t *mask, uint16_t *Y, int32_t T,
                           int32_t n, hipStream_t st);
-// prediction only: the four conv layers per tile in LDS and the head (zpart [T][tiles][128])
+// prediction only: the four conv layers per tile in LDS, pooled into per-tile channel sums
+// (zpart [T][tiles][128]); then the pooled mean and the head
 int32_t nn_fused_tiles(int32_t n);
 hipError_t nn_launch_fwd_fused(const uint16_t *X, const NnWeights &w, const float *P, int32_t T,
-                               int32_t n, float *zpart, float *z, float *a, float *y, float *pred,
-                               double shift, double scale, hipStream_t st);
+                               int32_t n, float *zpart, hipStream_t st);
+hipError_t nn_launch_head_pool(const float *zpart, int32_t T, int32_t n, const float *P, float *z,
+                               float *a, float *y, float *pred, double shift, double scale,
+                               hipStream_t st);
 hipError_t nn_launch_head_fwd(const uint16_t *H4, int32_t T, int32_t n, const float *P, float *z,
                               float *a, float *y, float *pred, double shift, double scale,
                               hipStream_t st);

@@ -254,78 +254,91 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
 // (training keeps every layer's output for the backward pass). The input tile carries a halo
 // of 8 rows (2 per layer); layer l's output row r is position j0 - 6 + 2l + r, and rows at
 // positions outside the tour are set to zero, which is the zero padding of the next layer. Each
-// layer is a GEMM over 5 m-tiles of 16 rows x 128 channels: wave w owns channel tiles 2w, 2w+1
-// and reads just those weight fragments from L2, 4 K blocks ahead, so the K loop has no barrier
-// (one per layer); the activation fragments of the next K block are read from LDS while the
-// current one runs. The last layer rounds its outputs to
-// bfloat16 (as the layer-by-layer path stores them) and sums them per channel over the tile's
-// positions, in a fixed order, into zpart[t][tile][co].
-constexpr int kFuseTP = 64;
-constexpr int kFuseRows = kFuseTP + 20;     // rows of every LDS activation buffer
+// layer is a GEMM over 16-row m-tiles x 128 channels: wave p owns channel pair p (tiles 2p and
+// 2p + 1) over every m-tile, so each weight fragment it reads from L2 (in fragment order, 1 KB
+// contiguous per tile and K block) feeds all the m-tiles of the layer. The fragments form one stream
+// over the four layers, kept kFuseDepth K blocks ahead in a register ring, so a layer starts
+// with its first fragments already loaded and the K loop has no barrier (one per layer). The
+// input tile shares its LDS with the second hidden buffer, which is first written by layer 2,
+// after every wave has passed layer 2's barrier and so finished reading the input. The last
+// layer rounds its outputs to bfloat16 (as the layer-by-layer path stores them) and sums them
+// per channel over the tile's positions, in a fixed order, into zpart[t][tile][co].
+constexpr int kFuseTP = 128;                       // output positions per tile
+constexpr int kFuseMT = (kFuseTP + 12 + 15) / 16;  // m-tiles of layers 1..3 (TP + 12, 8, 4 rows)
+constexpr int kFuseRows = kFuseMT * 16 + 4;        // rows of an LDS buffer (taps read 4 past)
+constexpr int kFuseDepth = 2;                      // K blocks of weight fragments in flight
+constexpr int kFuseThreads = 256;                  // four waves, one per channel pair
+constexpr int kFuseOcc = 2;                        // waves per SIMD the register budget allows
 constexpr int kFuseStrideX = kNnCi0 + 8;    // bf16 per input row (16 bytes of padding)
 constexpr int kFuseStrideH = kNnWidth + 8;  // bf16 per hidden row (16 bytes of padding)
+static_assert(kFuseTP % 16 == 0, "the last layer covers the tile in whole m-tiles");
 
-template <int CI, bool POOL>
-__device__ __forceinline__ void fused_layer(const uint16_t *in, uint16_t *out,
-                                            const uint16_t *Wt, const float *bias, int mtiles,
-                                            int pos0, int n, float *pool_out)
+struct FuseRing {
+    bf16x8 b0[kFuseDepth], b1[kFuseDepth];  // fragments of channel tiles 2p and 2p + 1
+};
+
+// Fragment kb of channel pair cp from the fragment-ordered weights Wg of a layer with K inputs.
+template <int K>
+__device__ __forceinline__ void fuse_frag(const uint16_t *Wg, int cp, int kb, bf16x8 &x0,
+                                          bf16x8 &x1)
+{
+    const int lane = threadIdx.x & 63;
+    const uint16_t *p = Wg + ((cp * (K / 32) + kb) * 2 * 64 + lane) * 8;
+    x0 = *reinterpret_cast<const bf16x8 *>(p);
+    x1 = *reinterpret_cast<const bf16x8 *>(p + 64 * 8);
+}
+
+// The MC m-tiles of one layer for channel pair cp. Fragment kb of this layer
+// sits in ring slot (R0 + kb) % depth; the slot it frees is refilled with the fragment depth
+// blocks later in the stream, which is in the next layer (weights Wn, CIN input channels; none
+// when CIN == 0) near the end. Without POOL the outputs go to `out`; with POOL, sum[h] receives
+// this lane's share of the channel sums of tile 2cp + h (its 4 rows of each m-tile).
+template <int CI, int MC, int R0, int CIN, bool POOL>
+__device__ __forceinline__ void fused_part(const uint16_t *in, uint16_t *out, const uint16_t *Wt,
+                                           const uint16_t *Wn, const float *bias, int pos0,
+                                           int n, int cp, FuseRing &ring, float (&sum)[2])
 {
     constexpr int K = kNnTaps * CI;
     constexpr int KB = K / 32;
+    constexpr int KN = kNnTaps * CIN;
+    constexpr int KBN = KN / 32;
+    constexpr int D = kFuseDepth;
     constexpr int SIN = CI == kNnCi0 ? kFuseStrideX : kFuseStrideH;
-    constexpr int DEPTH = 4;  // weight fragments in flight (read from L2, no LDS staging)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, kq = lane >> 4;
-    // this wave's two 16-channel tiles: columns (2 wave + h) * 16 + r16 of Wt[co][K]
-    const bf16x8 *w0 = reinterpret_cast<const bf16x8 *>(Wt + (long long)((2 * wave) * 16 + r16) * K +
-                                                         kq * 8);
-    const bf16x8 *w1 = w0 + (16 * K) / 8;
-    f32x4 acc[5][2];
+    f32x4 acc[MC][2];
 #pragma unroll
-    for (int mt = 0; mt < 5; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 b0[DEPTH], b1[DEPTH];
-#pragma unroll
-    for (int d = 0; d < DEPTH; ++d) {
-        if (d < KB) {
-            b0[d] = w0[d * 4];
-            b1[d] = w1[d * 4];
-        }
-    }
-    __syncthreads();  // the input rows of this layer are in LDS
-    bf16x8 a[5], an[5];
-    auto load_a = [&](int kb, bf16x8 (&dst)[5]) {
+    for (int mt = 0; mt < MC; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // activation fragment of m-tile mt for K block kb
+    auto frag_a = [&](int kb, int mt) {
         const int kk = kb * 32 + kq * 8;
         const int tap = kk / CI, ci = kk - tap * CI;
-#pragma unroll
-        for (int mt = 0; mt < 5; ++mt)
-            if (mt < mtiles)
-                dst[mt] = *reinterpret_cast<const bf16x8 *>(in + (mt * 16 + r16 + tap) * SIN + ci);
+        return *reinterpret_cast<const bf16x8 *>(in + (mt * 16 + r16 + tap) * SIN + ci);
     };
-    load_a(0, a);
+    bf16x8 a[MC];
+#pragma unroll
+    for (int mt = 0; mt < MC; ++mt) a[mt] = frag_a(0, mt);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-        if (kb + 1 < KB) load_a(kb + 1, an);
-        const bf16x8 bb0 = b0[kb % DEPTH], bb1 = b1[kb % DEPTH];
-        if (kb + DEPTH < KB) {
-            b0[kb % DEPTH] = w0[(kb + DEPTH) * 4];
-            b1[kb % DEPTH] = w1[(kb + DEPTH) * 4];
-        }
+        const int slot = (R0 + kb) % D;
+        const bf16x8 bb0 = ring.b0[slot], bb1 = ring.b1[slot];
+        if (kb + D < KB)
+            fuse_frag<K>(Wt, cp, kb + D, ring.b0[slot], ring.b1[slot]);
+        else if (kb + D - KB < KBN)
+            fuse_frag<KN>(Wn, cp, kb + D - KB, ring.b0[slot], ring.b1[slot]);
+        // each m-tile's next fragment is read as soon as its two products are issued
 #pragma unroll
-        for (int mt = 0; mt < 5; ++mt) {
-            if (mt < mtiles) {
-                acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb0, acc[mt][0], 0, 0, 0);
-                acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb1, acc[mt][1], 0, 0, 0);
-            }
+        for (int mt = 0; mt < MC; ++mt) {
+            acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb0, acc[mt][0], 0, 0, 0);
+            acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb1, acc[mt][1], 0, 0, 0);
+            if (kb + 1 < KB) a[mt] = frag_a(kb + 1, mt);
         }
-        if (kb + 1 < KB) {
-#pragma unroll
-            for (int mt = 0; mt < 5; ++mt) a[mt] = an[mt];
-        }
+        // keep the compiler from hoisting later blocks' reads into this one: their registers
+        // would push the wave past the budget of two waves per SIMD and into scratch
+        __builtin_amdgcn_sched_barrier(0);
     }
-    float sum[2] = {0.f, 0.f};
 #pragma unroll
-    for (int mt = 0; mt < 5; ++mt) {
-        if (mt >= mtiles) continue;
+    for (int mt = 0; mt < MC; ++mt) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = mt * 16 + kq * 4 + i;
@@ -333,7 +346,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t *in, uint16_t *out,
             const bool inside = pos >= 0 && pos < n;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int co = (2 * wave + h) * 16 + r16;
+                const int co = (2 * cp + h) * 16 + r16;
                 float v = acc[mt][h][i] + bias[co];
                 v = v > 0.f && inside ? v : 0.f;
                 const uint16_t bv = bf16_bits_f32(v);
@@ -344,30 +357,51 @@ __device__ __forceinline__ void fused_layer(const uint16_t *in, uint16_t *out,
             }
         }
     }
+}
+
+// One layer over MT m-tiles (see fused_part). With POOL the tile's channel sums go to
+// pool_out[128].
+template <int CI, int MT, int R0, int CIN, bool POOL>
+__device__ __forceinline__ void fused_layer(const uint16_t *in, uint16_t *out,
+                                            const uint16_t *Wt, const uint16_t *Wn,
+                                            const float *bias, int pos0, int n, float *pool_out,
+                                            FuseRing &ring)
+{
+    const int cp = threadIdx.x >> 6;
+    float sum[2] = {0.f, 0.f};
+    __syncthreads();  // the input rows of this layer are in LDS
+    fused_part<CI, MT, R0, CIN, POOL>(in, out, Wt, Wn, bias, pos0, n, cp, ring, sum);
     if (POOL) {
         // the 4 row groups of a column, added in a fixed order
+        const int lane = threadIdx.x & 63;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             float v = sum[h];
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
-            if (kq == 0) pool_out[(2 * wave + h) * 16 + r16] = v;
+            if (lane < 16) pool_out[(2 * cp + h) * 16 + lane] = v;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void nn_fwd_fused_kernel(const uint16_t *X, NnWeights w,
-                                                           const float *P, int32_t n,
-                                                           int32_t tiles, float *zpart)
+__global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(kFuseOcc)))
+void nn_fwd_fused_kernel(const uint16_t *X, NnWeights w, const float *P, int32_t n,
+                         int32_t tiles, float *zpart)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t xs[kFuseRows * kFuseStrideX];
     __shared__ __attribute__((aligned(16))) uint16_t ha[kFuseRows * kFuseStrideH];
     __shared__ __attribute__((aligned(16))) uint16_t hb[kFuseRows * kFuseStrideH];
+    uint16_t *xs = hb;  // the input tile, until layer 2 writes hb
     const int tid = threadIdx.x;
     const int t = blockIdx.x / tiles, k = blockIdx.x - t * tiles;
     const int j0 = k * kFuseTP;
+    const int cp = tid >> 6;
+    constexpr int KB1 = kNnTaps * kNnCi0 / 32, KBH = kNnTaps * kNnWidth / 32;
+    constexpr int D = kFuseDepth;
+    FuseRing ring;
+#pragma unroll
+    for (int d = 0; d < D; ++d) fuse_frag<kNnTaps * kNnCi0>(w.g[0], cp, d, ring.b0[d], ring.b1[d]);
     // input rows: position j0 - 8 + r (zero outside the tour), 32 channels as 4 chunks of 16 B
-    for (int e = tid; e < kFuseRows * 4; e += 256) {
+    for (int e = tid; e < kFuseRows * 4; e += kFuseThreads) {
         const int r = e >> 2, c = e & 3;
         const int pos = j0 - 8 + r;
         u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -376,12 +410,16 @@ __global__ __launch_bounds__(256) void nn_fwd_fused_kernel(const uint16_t *X, Nn
                                                 c * 8);
         *reinterpret_cast<u16x8 *>(xs + r * kFuseStrideX + c * 8) = v;
     }
-    // layers 1..3 over 5 m-tiles (76, 72, 68 rows used), layer 4 over the tile's 64 rows
-    fused_layer<kNnCi0, false>(xs, ha, w.f[0], P + nn_off_b(0), 5, j0 - 6, n, nullptr);
-    fused_layer<kNnWidth, false>(ha, hb, w.f[1], P + nn_off_b(1), 5, j0 - 4, n, nullptr);
-    fused_layer<kNnWidth, false>(hb, ha, w.f[2], P + nn_off_b(2), 5, j0 - 2, n, nullptr);
-    fused_layer<kNnWidth, true>(ha, nullptr, w.f[3], P + nn_off_b(3), 4, j0, n,
-                                zpart + ((long long)t * tiles + k) * kNnWidth);
+    fused_layer<kNnCi0, kFuseMT, 0, kNnWidth, false>(xs, ha, w.g[0], w.g[1], P + nn_off_b(0),
+                                                      j0 - 6, n, nullptr, ring);
+    fused_layer<kNnWidth, kFuseMT, KB1 % D, kNnWidth, false>(ha, hb, w.g[1], w.g[2],
+                                                             P + nn_off_b(1), j0 - 4, n, nullptr,
+                                                             ring);
+    fused_layer<kNnWidth, kFuseMT, (KB1 + KBH) % D, kNnWidth, false>(
+        hb, ha, w.g[2], w.g[3], P + nn_off_b(2), j0 - 2, n, nullptr, ring);
+    fused_layer<kNnWidth, kFuseTP / 16, (KB1 + 2 * KBH) % D, 0, true>(
+        ha, nullptr, w.g[3], nullptr, P + nn_off_b(3), j0, n,
+        zpart + ((long long)t * tiles + k) * kNnWidth, ring);
 }
 
 // Head from the per-tile sums: z[c] = (sum over tiles, in order) / n, then as nn_head_fwd_kernel.
@@ -651,6 +689,17 @@ __global__ __launch_bounds__(256) void nn_adam_kernel(float *P, float *m, float 
 
 // bf16 copies of the conv weights: Wf_l[co][tap * CI + ci] (forward) and, for layers 2..4,
 // Wb_l[ci][tap' * 128 + co] = W_l[4 - tap'][ci][co] (backward data). One thread per weight.
+// Position of weight (co, k) of a layer with K = 32 KB in MFMA fragment order: the 16-byte
+// B operand of lane kq * 16 + r16 for channel tile 2 cp + h and K block kb holds
+// k = 32 kb + 8 kq .. + 7 of channel co = (2 cp + h) * 16 + r16; the two tiles of a channel pair
+// and the 64 lanes are adjacent, so a wave reads one pair's fragment as 2 x 1 KB contiguous.
+__device__ __forceinline__ int nn_frag_index(int co, int k, int KB)
+{
+    const int cp = co >> 5, h = (co >> 4) & 1, r16 = co & 15;
+    const int kb = k >> 5, kq = (k >> 3) & 3, e = k & 7;
+    return (((cp * KB + kb) * 2 + h) * 64 + kq * 16 + r16) * 8 + e;
+}
+
 __global__ __launch_bounds__(256) void nn_pack_kernel(const float *P, NnWeights w)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
@@ -658,7 +707,9 @@ __global__ __launch_bounds__(256) void nn_pack_kernel(const float *P, NnWeights 
     if (e < n1) {
         const int tap = e / (kNnCi0 * kNnWidth), r = e % (kNnCi0 * kNnWidth);
         const int ci = r / kNnWidth, co = r % kNnWidth;
-        w.f[0][co * (kNnTaps * kNnCi0) + tap * kNnCi0 + ci] = bf16_bits_f32(P[nn_off_w(0) + e]);
+        const uint16_t b = bf16_bits_f32(P[nn_off_w(0) + e]);
+        w.f[0][co * (kNnTaps * kNnCi0) + tap * kNnCi0 + ci] = b;
+        w.g[0][nn_frag_index(co, tap * kNnCi0 + ci, kNnTaps * kNnCi0 / 32)] = b;
         return;
     }
     const int e2 = e - n1;
@@ -669,6 +720,7 @@ __global__ __launch_bounds__(256) void nn_pack_kernel(const float *P, NnWeights 
     const uint16_t b = bf16_bits_f32(P[nn_off_w(l) + r0]);
     w.f[l][co * (kNnTaps * kNnWidth) + tap * kNnWidth + ci] = b;
     w.b[l][ci * (kNnTaps * kNnWidth) + (kNnTaps - 1 - tap) * kNnWidth + co] = b;
+    w.g[l][nn_frag_index(co, tap * kNnWidth + ci, kNnTaps * kNnWidth / 32)] = b;
 }
 
 // ------------------------------------------------------------------------- top-k
@@ -916,16 +968,20 @@ hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *W
 int32_t nn_fused_tiles(int32_t n) { return (n + kFuseTP - 1) / kFuseTP; }
 
 hipError_t nn_launch_fwd_fused(const uint16_t *X, const NnWeights &w, const float *P, int32_t T,
-                               int32_t n, float *zpart, float *z, float *a, float *y, float *pred,
-                               double shift, double scale, hipStream_t st)
+                               int32_t n, float *zpart, hipStream_t st)
 {
     const int32_t tiles = nn_fused_tiles(n);
-    hipLaunchKernelGGL(nn_fwd_fused_kernel, dim3((unsigned)((long long)T * tiles)), dim3(256), 0,
-                       st, X, w, P, n, tiles, zpart);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nn_head_pool_kernel, dim3(T), dim3(128), 0, st, zpart, tiles, n, P, z, a, y,
-                       pred, shift, scale);
+    hipLaunchKernelGGL(nn_fwd_fused_kernel, dim3((unsigned)((long long)T * tiles)),
+                       dim3(kFuseThreads), 0, st, X, w, P, n, tiles, zpart);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_head_pool(const float *zpart, int32_t T, int32_t n, const float *P, float *z,
+                               float *a, float *y, float *pred, double shift, double scale,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(nn_head_pool_kernel, dim3(T), dim3(128), 0, st, zpart,
+                       nn_fused_tiles(n), n, P, z, a, y, pred, shift, scale);
     return hipGetLastError();
 }
 

@@ -88,6 +88,9 @@ def test_nn_null_handles_are_rejected(lib):
     assert lib.split_topk_smallest(null, None, 1, 1, None, None) == sg.SPLIT_E_INVAL
     assert lib.split_nn_screen(null, None, 1, 1, 1, None, 1, 1, 1, None, None, None, None, None,
                                None) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_timing_enable(null, 1) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_timing_get(null, None, None) == sg.SPLIT_E_INVAL
+    assert lib.split_nn_timing_reset(null) == sg.SPLIT_E_INVAL
     lib.split_nn_destroy(null)
     assert lib.split_search(null, None, None, 1, None, 1, 1, 1, 1, 1, 1.0, 1, 0, None, None, None,
                             0, None, None, None) == sg.SPLIT_E_INVAL

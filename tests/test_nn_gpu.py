@@ -266,11 +266,13 @@ def test_bad_tour_ids_are_rejected(sg, env):
     net.close()
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 130, 200])
+@pytest.mark.parametrize("n", [1, 15, 63, 64, 65, 95, 96, 97, 127, 128, 129, 130, 200, 257, 300,
+                               1000])
 def test_fused_prediction_across_tile_boundaries(sg, n):
-    # prediction runs the four layers per 64-position tile in LDS with an 8-row halo; tours
-    # shorter than, equal to and straddling tiles must give the layer-by-layer reference
-    Nn = 200
+    # prediction runs the four layers per tile of positions in LDS with an 8-row halo; tours
+    # shorter than, equal to and straddling tiles of any power-of-two or multiple-of-16 size
+    # must give the float64 reference of the network (1000: the screening workload's length)
+    Nn = 1000
     xy = gen.coords(52, Nn)
     ctx = sg.SplitContext(0)
     ctx.set_coords(xy)
@@ -298,4 +300,23 @@ def test_shortlist_is_topk_of_predict(sg, env):
     pred = net.predict(dc).cpu().numpy()
     idx = net.shortlist(dc, 37).cpu().numpy()
     assert np.array_equal(idx, np.sort(np.lexsort((np.arange(len(pred)), pred))[:37]))
+    net.close()
+
+
+def test_fused_kernel_timing_counts_one_launch_per_forward_pass(sg, env):
+    net = make_net(sg, env, seed=2)
+    cands = np.stack([gen.tour(46, N, NL, variant=v) for v in range(1, 2501)])
+    dc = torch.from_numpy(cands).cuda()
+    want = net.predict(dc).cpu().numpy()
+    net.timing(True)
+    net.timing_reset()
+    got = net.predict(dc).cpu().numpy()
+    ms, launches = net.timing_get()
+    assert launches == 3 and ms > 0.0  # 2500 tours in passes of 1024
+    assert np.array_equal(got, want)
+    net.timing(False)
+    net.predict(dc)
+    assert net.timing_get()[1] == 3
+    net.timing_reset()
+    assert net.timing_get() == (0.0, 0)
     net.close()
