@@ -20,7 +20,7 @@ static_assert(SPLIT_NN_PARAMS == kNnParams, "header and kernels disagree on the 
 namespace {
 
 constexpr int32_t kPredChunk = 1024;   // tours per forward pass when predicting many tours
-constexpr int32_t kWgradChunk = 1024;  // positions per weight-gradient partial sum
+constexpr int32_t kWgradChunk = 1024;  // padded rows per weight-gradient partial sum
 constexpr int32_t kExactChunk = 256;   // shortlisted tours per exact batch evaluation
 const char kMagic[8] = {'S', 'P', 'L', 'I', 'T', 'N', 'N', '1'};
 
@@ -278,8 +278,7 @@ split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, i
 // Loss terms and the full gradient into nn->G for the batch whose forward pass just ran.
 split_status backward(split_nn *nn, const float *labels, int32_t T, int32_t n, hipStream_t st)
 {
-    const int64_t M = (int64_t)T * n;
-    const int64_t chunks = (M + kWgradChunk - 1) / kWgradChunk;
+    const int64_t chunks = nn_wgrad_chunks(T, n, kWgradChunk);
     if (chunks > nn->cap_chunks) {
         NN_TRY(nn, hipDeviceSynchronize());
         nn->cap_chunks = 0;

@@ -75,6 +75,8 @@ hipError_t nn_launch_head_bwd(const float *labels, int32_t T, int32_t n, const f
                               const float *z, const float *a, const float *y, double shift,
                               double scale, float *da, float *dz, float *dy, float *loss_terms,
                               const uint16_t *H4, uint16_t *dP4, float *G, hipStream_t st);
+// number of weight-gradient partials for a batch: chunks of `chunk` padded rows
+int32_t nn_wgrad_chunks(int32_t T, int32_t n, int32_t chunk);
 hipError_t nn_launch_wgrad(int ci, const uint16_t *H, const uint16_t *dP, int32_t T, int32_t n,
                            int32_t chunk, int32_t chunks, float *partW, float *partB, float *G,
                            int32_t offW, int32_t offB, hipStream_t st);

@@ -581,75 +581,108 @@ __global__ __launch_bounds__(256) void nn_dp4_kernel(const float *dz, const uint
 
 // ------------------------------------------------------------------------- weight gradients
 
-// Partial dW[tap][ci][co] = sum over a chunk of positions of H[row j + tap][ci] * dP[row j + 2][co]
-// (padded rows), and for tap 0 / ci block 0 the partial bias gradient sum dP[row j + 2][co].
-// Grid (chunks, taps, CI / 32). A workgroup of 256 threads covers 32 ci x 128 co: thread
-// (ci quad, co quad) = (threadIdx / 32, threadIdx % 32) holds 4 x 4 sums. Positions are staged
-// through LDS 32 at a time.
+// Partial weight and bias gradients on the matrix cores. The sums run over the padded rows r of
+// the batch (R = T (n + 4) rows; the pre-activation gradient dP is zero on every padding row, so
+// those rows add nothing): dW[tap][ci][co] = sum_r H[r - 2 + tap][ci] * dP[r][co] and
+// db[co] = sum_r dP[r][co]. Workgroup (chunk c, slice s) takes rows 2 + c * chunk .. up to
+// R - 2 and input channels 32 s .. 32 s + 31, for every tap and output channel. It stages 64 rows
+// at a time in LDS, transposed so that the contracted index (rows) is contiguous: dP^T [co][k],
+// and one copy of H^T [ci][k] per tap, shifted by the tap, so that every fragment read is an
+// aligned 16-byte load. Wave w accumulates output channels 32 w .. 32 w + 31 for both ci tiles
+// and all taps (20 tiles). Slice 0 also sums the bias gradient, thread co over the staged rows
+// in order.
 template <int CI>
 __global__ __launch_bounds__(256) void nn_wgrad_kernel(const uint16_t *H, const uint16_t *dP,
-                                                       int32_t T, int32_t n, int32_t chunk,
-                                                       float *partW, float *partB)
+                                                       long long R, int32_t chunk, float *partW,
+                                                       float *partB)
 {
-    __shared__ float hs[32][32];
-    __shared__ float ps[32][kNnWidth];
-    const int tid = threadIdx.x;
-    const int tap = blockIdx.y, cib = blockIdx.z;
-    const long long M = (long long)T * n;
-    const long long p0 = (long long)blockIdx.x * chunk;
-    const long long p1 = p0 + chunk < M ? p0 + chunk : M;
-    const int cq = tid >> 5, oq = tid & 31;  // ci 4*cq .. +3 (of 32), co 4*oq .. +3
-    float acc[4][4] = {};
-    float bacc[4] = {};
-    for (long long pb = p0; pb < p1; pb += 32) {
-        // stage 32 positions: H rows (32 channels of this ci block) and dP rows (128 channels)
-        for (int e = tid; e < 32 * 32; e += 256) {
-            const int r = e >> 5, ci = e & 31;
-            const long long m = pb + r;
-            float v = 0.f;
-            if (m < p1) {
-                const long long t = m / n, j = m - t * n;
-                v = bf16_to_f32(H[(t * (n + 4) + j + tap) * CI + cib * 32 + ci]);
-            }
-            hs[r][ci] = v;
+    constexpr int KR = 64;      // rows per staged block
+    constexpr int SK = KR + 8;  // bf16 per transposed LDS row (16 bytes of padding)
+    __shared__ __attribute__((aligned(16))) uint16_t pt[kNnWidth * SK];
+    __shared__ __attribute__((aligned(16))) uint16_t ht[kNnTaps * 32 * SK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int slice = blockIdx.y;
+    const long long r0 = 2 + (long long)blockIdx.x * chunk;
+    const long long r1 = r0 + chunk < R - 2 ? r0 + chunk : R - 2;
+    f32x4 acc[kNnTaps][2][2];
+#pragma unroll
+    for (int t = 0; t < kNnTaps; ++t)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) acc[t][i][0] = acc[t][i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (long long rb = r0; rb < r1; rb += KR) {
+        __syncthreads();  // the previous block's fragments have been read
+        // dP rows rb .. rb + 63 (zero from r1 on), 16 chunks of 8 channels per row
+        for (int e = tid; e < KR * 16; e += 256) {
+            const int k = e % KR, c = e / KR;
+            const long long r = rb + k;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (r < r1) v = *reinterpret_cast<const u16x8 *>(dP + r * kNnWidth + c * 8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pt[(c * 8 + i) * SK + k] = v[i];
         }
-        for (int e = tid; e < 32 * kNnWidth; e += 256) {
-            const int r = e >> 7, co = e & 127;
-            const long long m = pb + r;
-            float v = 0.f;
-            if (m < p1) {
-                const long long t = m / n, j = m - t * n;
-                v = bf16_to_f32(dP[(t * (n + 4) + j + 2) * kNnWidth + co]);
+        // H rows rb - 2 .. rb + 65 (rb >= 2; zero past the last row), 4 chunks of 8 channels of
+        // this slice; row rb - 2 + k goes to position k - tap of tap's copy
+        for (int e = tid; e < (KR + 4) * 4; e += 256) {
+            const int k = e % (KR + 4), c = e / (KR + 4);
+            const long long h = rb - 2 + k;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (h < R) v = *reinterpret_cast<const u16x8 *>(H + h * CI + slice * 32 + c * 8);
+#pragma unroll
+            for (int t = 0; t < kNnTaps; ++t) {
+                const int kk = k - t;
+                if (kk >= 0 && kk < KR) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) ht[(t * 32 + c * 8 + i) * SK + kk] = v[i];
+                }
             }
-            ps[r][co] = v;
-        }
-        __syncthreads();
-        for (int r = 0; r < 32; ++r) {
-            float hv[4], pv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                hv[u] = hs[r][4 * cq + u];
-                pv[u] = ps[r][4 * oq + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) acc[u][w] += hv[u] * pv[w];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) bacc[w] += pv[w];
         }
         __syncthreads();
+        if (slice == 0 && tid < kNnWidth) {
+#pragma unroll
+            for (int k = 0; k < KR; k += 8) {
+                const u16x8 v = *reinterpret_cast<const u16x8 *>(pt + tid * SK + k);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bsum += bf16_to_f32(v[i]);
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < KR / 32; ++kb) {
+            const int kk = kb * 32 + kq * 8;
+            bf16x8 b[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const bf16x8 *>(pt + ((2 * wave + j) * 16 + r16) * SK + kk);
+#pragma unroll
+            for (int t = 0; t < kNnTaps; ++t) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const bf16x8 a =
+                        *reinterpret_cast<const bf16x8 *>(ht + (t * 32 + i * 16 + r16) * SK + kk);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[t][i][j] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[t][i][j], 0, 0, 0);
+                }
+            }
+        }
     }
-    float *dst = partW + (long long)blockIdx.x * (kNnTaps * CI * kNnWidth) +
-                 ((long long)tap * CI + cib * 32) * kNnWidth;
+    // lane (r16, kq) holds rows ci = 16 i + 4 kq + q, column co = 16 (2 wave + j) + r16
+    float *dst = partW + (long long)blockIdx.x * (kNnTaps * CI * kNnWidth);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < kNnTaps; ++t)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) dst[(4 * cq + u) * kNnWidth + 4 * oq + w] = acc[u][w];
-    if (tap == 0 && cib == 0 && cq == 0) {
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) partB[(long long)blockIdx.x * kNnWidth + 4 * oq + w] = bacc[w];
-    }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ci = slice * 32 + i * 16 + kq * 4 + q;
+                    const int co = (2 * wave + j) * 16 + r16;
+                    dst[((long long)t * CI + ci) * kNnWidth + co] = acc[t][i][j][q];
+                }
+    if (slice == 0 && tid < kNnWidth) partB[(long long)blockIdx.x * kNnWidth + tid] = bsum;
 }
 
 // G[offW + e] = sum over chunks of partW[chunk][e] (e < count), G[offB + c] likewise for the bias
@@ -1012,16 +1045,23 @@ hipError_t nn_launch_head_bwd(const float *labels, int32_t T, int32_t n, const f
     return hipGetLastError();
 }
 
+int32_t nn_wgrad_chunks(int32_t T, int32_t n, int32_t chunk)
+{
+    const long long rows = (long long)T * (n + 4) - 4;  // rows 2 .. T (n + 4) - 3
+    return (int32_t)((rows + chunk - 1) / chunk);
+}
+
 hipError_t nn_launch_wgrad(int ci, const uint16_t *H, const uint16_t *dP, int32_t T, int32_t n,
                            int32_t chunk, int32_t chunks, float *partW, float *partB, float *G,
                            int32_t offW, int32_t offB, hipStream_t st)
 {
-    const dim3 g(chunks, kNnTaps, ci / 32), b(256);
+    if (chunks != nn_wgrad_chunks(T, n, chunk)) return hipErrorInvalidValue;
+    const long long R = (long long)T * (n + 4);
+    const dim3 g(chunks, ci / 32), b(256);
     if (ci == kNnCi0)
-        hipLaunchKernelGGL(nn_wgrad_kernel<kNnCi0>, g, b, 0, st, H, dP, T, n, chunk, partW, partB);
+        hipLaunchKernelGGL(nn_wgrad_kernel<kNnCi0>, g, b, 0, st, H, dP, R, chunk, partW, partB);
     else if (ci == kNnWidth)
-        hipLaunchKernelGGL(nn_wgrad_kernel<kNnWidth>, g, b, 0, st, H, dP, T, n, chunk, partW,
-                           partB);
+        hipLaunchKernelGGL(nn_wgrad_kernel<kNnWidth>, g, b, 0, st, H, dP, R, chunk, partW, partB);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
