@@ -139,6 +139,29 @@ def test_gradient_matches_reference_tightly_without_cancellation(sg, env, n):
     net.close()
 
 
+def test_gradient_across_weight_gradient_chunks(sg, env):
+    # 60 tours of 40 positions: 60 * 44 - 4 = 2636 padded rows, i.e. three partial sums of 1024
+    # rows (the last one ragged) whose 64-row blocks straddle tour boundaries
+    net = make_net(sg, env)
+    q = positive_params(61)
+    net.set_params(q)
+    tours = np.stack([gen.tour(23, N, NL, variant=v) for v in range(1, 61)])
+    mu, sd = nnref.demand_stats(env["dem"])
+    Xs = [nnref.features(t, env["d"], mu, sd, Q, L, xy=env["xy"]) for t in tours]
+    y_ref = nnref.forward(q.astype(np.float64), Xs, bf16=True)
+    labels = (1000.0 + 50.0 * (y_ref - 0.5)).astype(np.float32)
+    g, loss = net.gradient(torch.from_numpy(tours).cuda(), torch.from_numpy(labels).cuda())
+    loss_ref, g_ref = nnref.loss_and_grad(q.astype(np.float64), Xs,
+                                          (labels.astype(np.float64) - 1000.0) / 50.0, bf16=True)
+    errs = grad_errors(g, g_ref)
+    print("[nn] 3 gradient chunks: " + ", ".join(f"{k} {e:.1e}" for k, (e, _) in errs.items()),
+          flush=True)
+    assert abs(loss - loss_ref) <= 1e-4 * (1 + loss_ref)
+    for name, (e, _) in errs.items():
+        assert e <= 2e-3, name
+    net.close()
+
+
 def test_gradient_matches_reference_with_random_weights(sg, env):
     net = make_net(sg, env)
     p = net.params().astype(np.float64)

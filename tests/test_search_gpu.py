@@ -74,6 +74,24 @@ def test_surrogate_search_shortlists_a_pool(env):
     nn.close()
 
 
+def test_surrogate_search_with_a_pool_of_several_prediction_passes(env):
+    # 2500 candidates per iteration: three forward passes of up to 1024 tours, built on the
+    # device from the incumbent and the moves; the run is deterministic
+    sg = env["sg"]
+    nn = sg.SplitNN(env["ctx"], seed=5, length_scale=1000.0)
+    nn.set_scenarios(env["ddem"], Q)
+    m0 = exact_mean(env, env["tour0"])
+    nn.set_norm(m0, 0.05 * m0)
+    runs = [sg.search(env["ctx"], env["tour0"], env["ddem"], Q, batch=24, pool=2500, nn=nn,
+                      budget_s=60.0, max_iters=6, seed=13) for _ in range(2)]
+    for r in runs:
+        check_result(env, r, 24)
+        assert r["predicted"] == 6 * 2500
+    assert np.array_equal(runs[0]["best_tour"], runs[1]["best_tour"])
+    assert [m for _, m in runs[0]["trace"]] == [m for _, m in runs[1]["trace"]]
+    nn.close()
+
+
 def test_time_budget_stops_the_search(env):
     sg = env["sg"]
     r = sg.search(env["ctx"], env["tour0"], env["ddem"], Q, batch=8, budget_s=0.0, seed=1)
