@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsplitgpu.so")
 
 SPLIT_OK, SPLIT_E_INVAL, SPLIT_E_TOUR, SPLIT_E_DEMAND = 0, -1, -2, -3
 SPLIT_E_RANGE, SPLIT_E_HIP, SPLIT_E_NOMEM = -4, -5, -6
+SPLIT_MAX_N = 8192  # largest instance (customers) the library accepts
 FORM_AUTO, FORM_LANE, FORM_WAVE, FORM_MASK = 0, 1, 2, 3
 FORMS = {"auto": FORM_AUTO, "lane": FORM_LANE, "wave": FORM_WAVE, "mask": FORM_MASK}
 STATUS_NAMES = {0: "SPLIT_OK", -1: "SPLIT_E_INVAL", -2: "SPLIT_E_TOUR", -3: "SPLIT_E_DEMAND",

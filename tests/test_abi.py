@@ -78,6 +78,8 @@ def test_nn_parameter_count_matches_header_and_oracle():
     text = open(os.path.join(ROOT, "include", "split_nn.h")).read()
     count = int(re.search(r"#define SPLIT_NN_PARAMS (\d+)", text).group(1))
     assert count == sg.NN_PARAMS == nn.n_params()
+    split_h = open(os.path.join(ROOT, "include", "split.h")).read()
+    assert int(re.search(r"#define SPLIT_MAX_N (\d+)", split_h).group(1)) == sg.SPLIT_MAX_N
 
 
 def test_nn_null_handles_are_rejected(lib):

@@ -200,6 +200,22 @@ def test_maximum_capacity_and_run_twice_determinism(ctx):
     assert np.array_equal(c, c2)
 
 
+def test_maximum_instance_and_tour_length(ctx):
+    # the largest instance the boundary accepts, toured in full: n = N = SPLIT_MAX_N = 8192
+    import paper_2511_18022_amd as sg
+    N = sg.SPLIT_MAX_N
+    xy = gen.coords(71, N)
+    dem = gen.demand_uniform(71, N, 1100, 1, 40)
+    tour = gen.tour(71, N, N)
+    d = oracle.dist_matrix(xy)
+    for form in ("lane", "wave"):
+        print(f"[parity] n = N = {N}, S = 1100, form {form}", flush=True)
+        check_against_oracle(ctx, tour, dem, 500, d, form=form, xy=xy)
+    with pytest.raises(sg.SplitError) as ei:
+        ctx.set_coords(gen.coords(71, N + 1))
+    assert ei.value.status == sg.SPLIT_E_INVAL
+
+
 @pytest.mark.parametrize("form", ["lane", "wave", "mask"])
 @pytest.mark.parametrize("Q,lo,hi", [(16383, 4000, 16383), (16383, 1, 16383), (4681, 2000, 4681),
                                      (3000, 0, 400)])
