@@ -347,7 +347,7 @@ def test_fused_kernel_timing_counts_one_launch_per_forward_pass(sg, env):
 
 def test_screening_gain_over_the_method_without_the_network(sg):
     # The gain the surrogate brings: 1000-customer candidates around a 2-opt tour, labelled and
-    # judged by the exact Split over 2048 copula scenarios. A trained surrogate ranks them
+    # scored by the exact Split over 2048 copula scenarios. A trained surrogate ranks them
     # closely to the exact means, and its 5% shortlist holds a tour within 0.5% of the best that
     # exact evaluation of every candidate finds. An untrained surrogate (the same network
     # without the training) ranks them much worse.
