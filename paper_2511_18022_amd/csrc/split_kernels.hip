@@ -386,6 +386,12 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
 {
     const int p0 = c * kLB;
     const uint32_t lane8 = (uint32_t)lane << 3;
+    // every state's older-block lookup, issued up front (in bounds for any start; a lane whose
+    // window lies inside the block does not use its result)
+    uint32_t qd[kLB];
+    uint64_t qr[kLB];
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) query_issue(L, sCur[t], lane8, qd[t], qr[t]);
     int pre = kInf;
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
@@ -404,10 +410,7 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
                     if (p0 + j >= s) mm = min(mm, gb[j]);
                 m = mm;
             } else {
-                uint32_t dlv;
-                uint64_t recv;
-                query_issue(L, sCur[t], lane8, dlv, recv);
-                m = query_min(dlv, recv, pre);
+                m = query_min(qd[t], qr[t], pre);
             }
             g = w[i] + m;
         }
