@@ -405,9 +405,13 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
             if (s >= p0) {  // window inside the block, or empty (s == i: q_i > Q)
                 err |= (s >= i);
                 int mm = kInf;
+                if (s == p0) {
+                    mm = pre;  // the whole block so far (block 0 of a long-window tour)
+                } else {
 #pragma unroll
-                for (int j = 0; j < t; ++j)
-                    if (p0 + j >= s) mm = min(mm, gb[j]);
+                    for (int j = 0; j < t; ++j)
+                        if (p0 + j >= s) mm = min(mm, gb[j]);
+                }
                 m = mm;
             } else {
                 m = query_min(qd[t], qr[t], pre);
