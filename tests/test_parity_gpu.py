@@ -252,3 +252,42 @@ def test_async_calls_and_stats_get(ctx):
         assert np.array_equal(cost.cpu().numpy(), want)
     mom = oracle.moments(want)
     assert st.sum == mom["sum"] and st.var == mom["var"]
+
+
+def _random_case(k):
+    # a seeded mix of instance sizes, capacities and demand laws, including spiky demands (a few
+    # customers near the capacity among small ones) that make window starts jump
+    rng = np.random.default_rng(9000 + k)
+    N = int(rng.integers(1, 400))
+    n = int(rng.integers(1, N + 1))
+    S = int(rng.integers(1, 3000))
+    seed = 9000 + k
+    law = k % 4
+    if law == 0:
+        dem = gen.demand_uniform(seed, N, S, 0, int(rng.integers(1, 80)))
+    elif law == 1:
+        dem = gen.demand_poisson(seed, N, S, 2.0, float(rng.uniform(3.0, 40.0)), 16383)
+    elif law == 2:
+        dem = gen.demand_copula(seed, N, S, 0.6, float(rng.uniform(5.0, 40.0)), 0.5, 16383)
+    else:
+        # windows of 20..40 customers, and 5% of the customers at a third of Q or more
+        Q = int(rng.integers(400, 4000))
+        dem = gen.demand_uniform(seed, N, S, Q // 40, Q // 20)
+        big = gen.demand_uniform(seed + 1, N, S, Q // 3, Q)
+        rows = rng.random(N) < 0.05
+        dem[rows] = big[rows]
+    if law != 3:
+        qmax = max(1, int(dem.max()))
+        Q = int(min(16383, rng.integers(qmax, 8 * qmax + 1)))
+    dem = np.ascontiguousarray(np.clip(dem, 0, Q).astype(np.int16))
+    return gen.coords(seed, N), gen.tour(seed, N, n), dem, Q
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_seeded_random_instances_all_forms(ctx, k):
+    xy, tour, dem, Q = _random_case(k)
+    d = oracle.dist_matrix(xy)
+    print(f"[parity] random case {k}: N={len(xy) - 1} n={len(tour)} S={dem.shape[1]} Q={Q}",
+          flush=True)
+    for form in ("lane", "wave", "mask"):
+        check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
