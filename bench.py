@@ -153,10 +153,21 @@ def cpu_baseline(tours, d, demand, Q, S, threads: int, got_cost, target_cpu_s: f
         parity &= bool(np.array_equal(got_cost[k][:sample], want))
     evals = sample * len(tours)
     what = "the tour" if len(tours) == 1 else f"each of the {len(tours)} tours"
+    # the same oracle on one thread (the paper's single-threaded CPU comparison), over a
+    # quarter of the sample: about target_cpu_s / 4 of work
+    sample1 = max(64, (sample // 4) - (sample // 4) % 64)
+    dem1 = np.ascontiguousarray(demand[:, :sample1])
+    t0 = time.perf_counter()
+    for t in tours:
+        oracle.split(t, d, dem1, Q, threads=1)
+    el1 = time.perf_counter() - t0
     return {"value": evals / el, "unit": "scenario-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} of {S} scenarios of {what}, {threads} threads, "
                       f"{el:.2f} s wall",
-            "parity_vs_gpu_on_sample": parity}
+            "parity_vs_gpu_on_sample": parity,
+            "single_thread": {"value": sample1 * len(tours) / el1, "unit": "scenario-evals/s",
+                              "sample": f"first {sample1} scenarios of {what}, 1 thread, "
+                                        f"{el1:.2f} s"}}
 
 
 def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
