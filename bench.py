@@ -189,7 +189,7 @@ def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
 def timed_steps(ctx, step, wait, steps: int, warmup: int):
     """Warm-up steps, then `steps` timed steps between device synchronizations, with the
     dominant kernel of eager evaluations timed by HIP events on their stream. Returns
-    (ms per step, dominant-kernel average ms, kernel name, timed launches)."""
+    (ms per step, dominant-kernel average ms, kernel name, timed launches, median ms)."""
     import torch
     for _ in range(warmup):
         step()
@@ -205,8 +205,10 @@ def timed_steps(ctx, step, wait, steps: int, warmup: int):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kern_ms, launches, kname = ctx.timing_get()
+    samples = ctx.timing_samples()
     ctx.timing(False)
-    return el * 1e3 / steps, kern_ms / max(launches, 1), kname, launches
+    median = float(sorted(samples)[len(samples) // 2]) if len(samples) else None
+    return el * 1e3 / steps, kern_ms / max(launches, 1), kname, launches, median
 
 
 def exact_means(ctx, tours, dem, Q, chunk: int = 256):
@@ -545,15 +547,15 @@ def main():
             ctx.eval(w.tour, dem, w.Q, cost=cost, sync=False)
 
     # eager evaluations: the dominant kernel's duration for the roofline
-    ms_eager, kern_avg_ms, kname, launches = timed_steps(ctx, step, ctx.batch_stats, args.steps,
-                                                         args.warmup)
+    ms_eager, kern_avg_ms, kname, launches, kern_med_ms = timed_steps(
+        ctx, step, ctx.batch_stats, args.steps, args.warmup)
     stats, status = ctx.batch_stats()
     ms_step = ms_eager
     if launch == "graph":
         g = ctx.graph(T, sum(len(t) for t in tours), dem, w.Q,
                       cost=cost if batch else cost.view(1, -1))
-        ms_step, _, _, _ = timed_steps(ctx, lambda: g.launch(tours), g.stats, args.steps,
-                                       args.warmup)
+        ms_step, _, _, _, _ = timed_steps(ctx, lambda: g.launch(tours), g.stats, args.steps,
+                                          args.warmup)
         gstats, gstatus = g.stats()
         assert [s.sum for s in gstats] == [s.sum for s in stats] and gstatus == status
         g.close()
@@ -616,6 +618,7 @@ def main():
         roof["traffic"] = measured_traffic(w.name, w.S)
     if roof is not None:
         roof.update({"kernel": kname, "kernel_avg_ms": kern_avg_ms,
+                     "kernel_median_ms": kern_med_ms,
                      "algorithmic_bytes_per_launch": algo_bytes})
     out = {
         "metric": METRIC_BATCH if batch else METRIC,

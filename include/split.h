@@ -246,6 +246,10 @@ split_status split_timing_enable(split_ctx *ctx, int enable);
 split_status split_timing_get(split_ctx *ctx, double *ms_total, int64_t *launches,
                               const char **kernel_name);
 split_status split_timing_reset(split_ctx *ctx);
+/* The duration of every timed launch since the last reset, in order: ms HOST float [cap]
+ * receives the first min(cap, *count) of them (ms may be NULL when cap is 0); *count receives
+ * how many there are. Waits for the last call. */
+split_status split_timing_samples(split_ctx *ctx, float *ms, int64_t cap, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -27,8 +27,8 @@ EXPORTED = [
     "split_ctx_create", "split_ctx_destroy", "split_last_error", "split_instance_set_coords",
     "split_instance_set_dist", "split_eval", "split_stats_get", "split_eval_batch",
     "split_batch_stats_get", "split_set_form", "split_timing_enable", "split_timing_get",
-    "split_timing_reset", "split_tuning_set", "split_tuning_get", "split_autotune",
-    "split_graph_create", "split_graph_launch", "split_graph_stats", "split_graph_destroy",
+    "split_timing_reset", "split_timing_samples", "split_tuning_set", "split_tuning_get",
+    "split_autotune", "split_graph_create", "split_graph_launch", "split_graph_stats", "split_graph_destroy",
     # include/split_nn.h
     "split_nn_create", "split_nn_destroy", "split_nn_params_get", "split_nn_params_set",
     "split_nn_set_norm", "split_nn_set_scenarios", "split_nn_predict", "split_nn_gradient",
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_char_p)]
     lib.split_timing_reset.argtypes = [P]
+    lib.split_timing_samples.argtypes = [P, P, i64, ctypes.POINTER(i64)]
     lib.split_tuning_set.argtypes = [P, ctypes.POINTER(SplitTuningC)]
     lib.split_tuning_get.argtypes = [P, ctypes.POINTER(SplitTuningC)]
     lib.split_autotune.argtypes = [P, P, P, i32, P, i64, i64, i32, P, i64, i32, P,
@@ -387,6 +388,17 @@ class SplitContext:
 
     def timing_reset(self):
         self._check(self._lib.split_timing_reset(self._h))
+
+    def timing_samples(self):
+        """Durations (ms) of every timed launch since the last reset, in order."""
+        np = _np()
+        n = ctypes.c_int64()
+        self._check(self._lib.split_timing_samples(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float32)
+        if n.value:
+            self._check(self._lib.split_timing_samples(
+                self._h, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n)))
+        return out
 
     def timing_get(self):
         ms, n = ctypes.c_double(), ctypes.c_int64()

@@ -134,6 +134,7 @@ struct split_ctx {
     size_t tpairs_used = 0;
     double ms_acc = 0.0;
     int64_t launches = 0;
+    std::vector<float> ms_samples;  // per timed launch since the last reset
     const char *tname = "";
 };
 
@@ -298,6 +299,7 @@ split_status collect_timing(split_ctx *ctx)
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tpairs[k].first, ctx->tpairs[k].second));
         ctx->ms_acc += ms;
         ctx->launches += 1;
+        ctx->ms_samples.push_back(ms);
     }
     ctx->tpairs_used = 0;
     return SPLIT_OK;
@@ -950,7 +952,22 @@ split_status split_timing_reset(split_ctx *ctx)
     split_status st = collect_timing(ctx);
     ctx->ms_acc = 0.0;
     ctx->launches = 0;
+    ctx->ms_samples.clear();
     return st;
+}
+
+split_status split_timing_samples(split_ctx *ctx, float *ms, int64_t cap, int64_t *count)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    if (cap < 0 || (cap > 0 && !ms))
+        return fail(ctx, SPLIT_E_INVAL, "split_timing_samples: need cap >= 0 and ms for cap > 0");
+    DeviceGuard g(ctx->device);
+    split_status st = collect_timing(ctx);
+    if (st != SPLIT_OK) return st;
+    const int64_t n = (int64_t)ctx->ms_samples.size();
+    for (int64_t k = 0; k < n && k < cap; ++k) ms[k] = ctx->ms_samples[(size_t)k];
+    if (count) *count = n;
+    return SPLIT_OK;
 }
 
 // ------------------------------------------------------------------------- graphs

@@ -46,6 +46,7 @@ def test_null_context_is_rejected_without_touching_the_gpu(lib):
     assert lib.split_eval(null, None, 1, None, 1, 1, 1, None, None, None) == sg.SPLIT_E_INVAL
     assert lib.split_set_form(null, 1) == sg.SPLIT_E_INVAL
     assert lib.split_timing_enable(null, 1) == sg.SPLIT_E_INVAL
+    assert lib.split_timing_samples(null, None, 0, None) == sg.SPLIT_E_INVAL
     assert lib.split_stats_get(null, None) == sg.SPLIT_E_INVAL
     assert lib.split_ctx_create(0, None) == sg.SPLIT_E_INVAL
     assert lib.split_last_error(null) == b"null context"

@@ -291,3 +291,24 @@ def test_seeded_random_instances_all_forms(ctx, k):
           flush=True)
     for form in ("lane", "wave", "mask"):
         check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
+
+
+def test_kernel_timing_totals_and_samples(ctx):
+    # the bench's dominant-kernel timing: one sample per timed evaluation, summing to the total
+    w = gen.make_workload("poisson-n200", S=5000)
+    ctx.set_coords(w.xy)
+    ctx.set_form("lane")
+    dem = torch.from_numpy(w.demand).cuda()
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(5):
+        ctx.eval(w.tour, dem, w.Q, sync=False)
+    total, launches, name = ctx.timing_get()
+    samples = ctx.timing_samples()
+    assert name == "split_lane_kernel" and launches == 5 and len(samples) == 5
+    assert np.all(samples > 0) and abs(float(samples.sum()) - total) <= 1e-3 * total + 1e-6
+    ctx.timing(False)
+    ctx.eval(w.tour, dem, w.Q)
+    assert len(ctx.timing_samples()) == 5  # untimed calls add nothing
+    ctx.timing_reset()
+    assert len(ctx.timing_samples()) == 0 and ctx.timing_get()[:2] == (0.0, 0)
