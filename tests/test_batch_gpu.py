@@ -165,3 +165,32 @@ def test_every_tail_length_stays_in_the_lane_kernel(ctx):
     print(f"[batch] tail lengths {lens}", flush=True)
     _, stats = check_batch(ctx, tours, b.demand, b.Q, d, form="lane", xy=b.xy)
     assert [s.n_fallback for s in stats] == [0] * len(tours)
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_seeded_random_batches_under_launch_choices(ctx, k):
+    # random batches (uneven subset tours, some of a single customer) under a different launch
+    # choice each: one workgroup per item or a persistent queue, longest-first or given order,
+    # the lane or the wave form; every tour matches the oracle
+    import paper_2511_18022_amd as sg
+    rng = np.random.default_rng(7000 + k)
+    N = int(rng.integers(2, 300))
+    S = int(rng.integers(1, 2500))
+    T = int(rng.integers(1, 40))
+    xy = gen.coords(7000 + k, N)
+    Q = int(rng.integers(60, 600))
+    dem = np.clip(gen.demand_uniform(7000 + k, N, S, 0, Q // int(rng.integers(3, 30))), 0, Q)
+    tours = [gen.tour(7000 + k, N, int(rng.integers(1, N + 1)), variant=v) for v in range(T)]
+    choices = [(sg.FORM_LANE, 0, 0), (sg.FORM_LANE, 8, 1), (sg.FORM_LANE, 2, 0),
+               (sg.FORM_LANE, 1, 1), (sg.FORM_WAVE, 0, 0), (sg.FORM_LANE, 4, 0),
+               (sg.FORM_LANE, 0, 1), (sg.FORM_WAVE, 0, 1)]
+    form, per_cu, order = choices[k]
+    print(f"[batch] random case {k}: N={N} S={S} T={T} Q={Q} form {form} per_cu {per_cu} "
+          f"order {order}", flush=True)
+    ctx.set_coords(xy)
+    ctx.set_tuning(sg.SplitTuning(form, per_cu, order, 0))
+    try:
+        check_batch(ctx, tours, np.ascontiguousarray(dem.astype(np.int16)), Q,
+                    oracle.dist_matrix(xy), form={sg.FORM_LANE: "lane", sg.FORM_WAVE: "wave"}[form])
+    finally:
+        ctx.set_tuning(sg.SplitTuning(sg.FORM_AUTO, 0, 0, 0))
