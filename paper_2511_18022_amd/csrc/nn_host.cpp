@@ -440,7 +440,9 @@ split_status split_nn_create(split_ctx *ctx, uint64_t seed, double length_scale,
     for (float **p : {&nn->P, &nn->m, &nn->v, &nn->G})
         ok = ok && hipMalloc(p, sizeof(float) * kNnParams) == hipSuccess;
     ok = ok && hipMalloc(&nn->w.f[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess &&
-         hipMalloc(&nn->w.g[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess;
+         hipMalloc(&nn->w.g[0], sizeof(uint16_t) * kNnSizeW1) == hipSuccess &&
+         // the fused kernel's packed layer-1 weights: padding entries are never written
+         hipMemset(nn->w.g[0], 0, sizeof(uint16_t) * kNnSizeW1) == hipSuccess;
     for (int l = 1; l < 4; ++l)
         ok = ok && hipMalloc(&nn->w.f[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess &&
              hipMalloc(&nn->w.b[l], sizeof(uint16_t) * kNnSizeWl) == hipSuccess &&

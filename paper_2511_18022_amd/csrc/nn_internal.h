@@ -13,6 +13,7 @@ namespace splitgpu {
 
 constexpr int kNnTaps = 5;
 constexpr int kNnCi0 = 32;     // input channels of layer 1 (8 features, zero-padded)
+constexpr int kNnFeatures = 8;  // the features: channels 0..7 of layer 1's input
 constexpr int kNnWidth = 128;  // channels of every conv layer and of the MLP
 
 constexpr int kNnSizeW1 = kNnTaps * kNnCi0 * kNnWidth;

@@ -269,9 +269,15 @@ constexpr int kFuseRows = kFuseMT * 16 + 4;        // rows of an LDS buffer (tap
 constexpr int kFuseDepth = 2;                      // K blocks of weight fragments in flight
 constexpr int kFuseThreads = 256;                  // four waves, one per channel pair
 constexpr int kFuseOcc = 2;                        // waves per SIMD the register budget allows
+constexpr int kFuseK1 = 64;  // layer 1's K: 5 taps x 8 features, zero-padded to 2 blocks of 32
 constexpr int kFuseStrideX = kNnCi0 + 8;    // bf16 per input row (16 bytes of padding)
 constexpr int kFuseStrideH = kNnWidth + 8;  // bf16 per hidden row (16 bytes of padding)
 static_assert(kFuseTP % 16 == 0, "the last layer covers the tile in whole m-tiles");
+static_assert(kNnFeatures == 8 && kNnTaps * kNnFeatures <= kFuseK1,
+              "a tap's features are one 16-byte fragment; the taps fit layer 1's packed K");
+
+// K of a layer with CI input channels in the fused kernel (layer 1 packs its 8 features)
+__host__ __device__ constexpr int fuse_k(int ci) { return ci == kNnCi0 ? kFuseK1 : kNnTaps * ci; }
 
 struct FuseRing {
     bf16x8 b0[kFuseDepth], b1[kFuseDepth];  // fragments of channel tiles 2p and 2p + 1
@@ -298,9 +304,9 @@ __device__ __forceinline__ void fused_part(const uint16_t *in, uint16_t *out, co
                                            const uint16_t *Wn, const float *bias, int pos0,
                                            int n, int cp, FuseRing &ring, float (&sum)[2])
 {
-    constexpr int K = kNnTaps * CI;
+    constexpr int K = fuse_k(CI);
     constexpr int KB = K / 32;
-    constexpr int KN = kNnTaps * CIN;
+    constexpr int KN = CIN ? fuse_k(CIN) : 0;
     constexpr int KBN = KN / 32;
     constexpr int D = kFuseDepth;
     constexpr int SIN = CI == kNnCi0 ? kFuseStrideX : kFuseStrideH;
@@ -309,9 +315,17 @@ __device__ __forceinline__ void fused_part(const uint16_t *in, uint16_t *out, co
     f32x4 acc[MC][2];
 #pragma unroll
     for (int mt = 0; mt < MC; ++mt) acc[mt][0] = acc[mt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // activation fragment of m-tile mt for K block kb
+    // activation fragment of m-tile mt for K block kb: for layer 1, k = 8 tap + feature (taps
+    // past the fifth are zero); otherwise k = CI tap + channel
     auto frag_a = [&](int kb, int mt) {
         const int kk = kb * 32 + kq * 8;
+        if (CI == kNnCi0) {
+            const int tap = kk / kNnFeatures;
+            const int tc = tap < kNnTaps ? tap : kNnTaps - 1;
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(in + (mt * 16 + r16 + tc) * SIN);
+            const bf16x8 z = {};
+            return tap < kNnTaps ? v : z;
+        }
         const int tap = kk / CI, ci = kk - tap * CI;
         return *reinterpret_cast<const bf16x8 *>(in + (mt * 16 + r16 + tap) * SIN + ci);
     };
@@ -395,20 +409,19 @@ void nn_fwd_fused_kernel(const uint16_t *X, NnWeights w, const float *P, int32_t
     const int t = blockIdx.x / tiles, k = blockIdx.x - t * tiles;
     const int j0 = k * kFuseTP;
     const int cp = tid >> 6;
-    constexpr int KB1 = kNnTaps * kNnCi0 / 32, KBH = kNnTaps * kNnWidth / 32;
+    constexpr int KB1 = kFuseK1 / 32, KBH = kNnTaps * kNnWidth / 32;
     constexpr int D = kFuseDepth;
     FuseRing ring;
 #pragma unroll
-    for (int d = 0; d < D; ++d) fuse_frag<kNnTaps * kNnCi0>(w.g[0], cp, d, ring.b0[d], ring.b1[d]);
-    // input rows: position j0 - 8 + r (zero outside the tour), 32 channels as 4 chunks of 16 B
-    for (int e = tid; e < kFuseRows * 4; e += kFuseThreads) {
-        const int r = e >> 2, c = e & 3;
+    for (int d = 0; d < D; ++d) fuse_frag<kFuseK1>(w.g[0], cp, d, ring.b0[d], ring.b1[d]);
+    // input rows: position j0 - 8 + r (zero outside the tour), the 8 features (16 bytes; the
+    // zero channels of the input are not needed with layer 1's packed K)
+    for (int r = tid; r < kFuseRows; r += kFuseThreads) {
         const int pos = j0 - 8 + r;
         u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         if (pos >= 0 && pos < n)
-            v = *reinterpret_cast<const u16x8 *>(X + ((long long)t * (n + 4) + pos + 2) * kNnCi0 +
-                                                c * 8);
-        *reinterpret_cast<u16x8 *>(xs + r * kFuseStrideX + c * 8) = v;
+            v = *reinterpret_cast<const u16x8 *>(X + ((long long)t * (n + 4) + pos + 2) * kNnCi0);
+        *reinterpret_cast<u16x8 *>(xs + r * kFuseStrideX) = v;
     }
     fused_layer<kNnCi0, kFuseMT, 0, kNnWidth, false>(xs, ha, w.g[0], w.g[1], P + nn_off_b(0),
                                                       j0 - 6, n, nullptr, ring);
@@ -742,7 +755,8 @@ __global__ __launch_bounds__(256) void nn_pack_kernel(const float *P, NnWeights 
         const int ci = r / kNnWidth, co = r % kNnWidth;
         const uint16_t b = bf16_bits_f32(P[nn_off_w(0) + e]);
         w.f[0][co * (kNnTaps * kNnCi0) + tap * kNnCi0 + ci] = b;
-        w.g[0][nn_frag_index(co, tap * kNnCi0 + ci, kNnTaps * kNnCi0 / 32)] = b;
+        if (ci < kNnFeatures)  // the fused kernel's packed K (the rest of w.g[0] stays zero)
+            w.g[0][nn_frag_index(co, tap * kNnFeatures + ci, kFuseK1 / 32)] = b;
         return;
     }
     const int e2 = e - n1;
