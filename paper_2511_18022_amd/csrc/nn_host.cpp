@@ -74,6 +74,8 @@ struct split_nn {
     int64_t cap_chunks = 0;
     float *zpart = nullptr;  // prediction: per-tile channel sums [T][tiles][128]
     int64_t cap_zpart = 0;
+    uint16_t *Xp = nullptr;  // prediction: packed features [T][n][8]
+    int64_t cap_xp = 0;      // positions
     int32_t *err = nullptr;
     int32_t *h_err = nullptr;  // pinned
     // training batches
@@ -141,11 +143,11 @@ bool instance_of(split_nn *nn, NnInstance *in, int64_t *max_arc)
     return true;
 }
 
-// Activation buffers for T tours of length n (padding rows cleared for this n) and the
-// per-tour head buffers. Growing waits for enqueued work.
-split_status ensure_act(split_nn *nn, int32_t T, int32_t n, hipStream_t st)
+// The per-tour head buffers and, with `layers` (training), the activation buffers for T tours
+// of length n (padding rows cleared for this n). Growing waits for enqueued work.
+split_status ensure_act(split_nn *nn, int32_t T, int32_t n, bool layers, hipStream_t st)
 {
-    const int64_t rows = (int64_t)T * (n + 4);
+    const int64_t rows = layers ? (int64_t)T * (n + 4) : 0;
     if (rows > nn->cap_rows) {
         NN_TRY(nn, hipDeviceSynchronize());
         const int64_t cap = rows + rows / 4;
@@ -157,7 +159,7 @@ split_status ensure_act(split_nn *nn, int32_t T, int32_t n, hipStream_t st)
         nn->cap_rows = cap;
         nn->zero_n = -1;
     }
-    if (nn->zero_n != n) {
+    if (layers && nn->zero_n != n) {
         // padding rows are never written by the kernels: clear whole buffers for this layout
         NN_TRY(nn, hipMemsetAsync(nn->X, 0, sizeof(uint16_t) * nn->cap_rows * kNnCi0, st));
         for (int l = 0; l < 4; ++l)
@@ -244,9 +246,8 @@ split_status timing_begin(split_nn *nn, hipStream_t st, hipEvent_t *stop)
 split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, int32_t T,
                      int32_t n, float *pred, hipStream_t st)
 {
-    split_status s = ensure_act(nn, T, n, st);
+    split_status s = ensure_act(nn, T, n, pred == nullptr, st);
     if (s != SPLIT_OK) return s;
-    NN_TRY(nn, nn_launch_features(in, tours, T, n, nn->musd, nn->Q, nn->L, nn->X, nn->err, st));
     if (pred) {
         const int64_t need = (int64_t)T * nn_fused_tiles(n) * kNnWidth;
         if (need > nn->cap_zpart) {
@@ -256,15 +257,28 @@ split_status forward(split_nn *nn, const NnInstance &in, const int32_t *tours, i
                 return ctx_fail(nn->ctx, SPLIT_E_NOMEM, "surrogate: pooling buffer failed");
             nn->cap_zpart = need;
         }
+        const int64_t pos = (int64_t)T * n;
+        if (pos > nn->cap_xp) {
+            NN_TRY(nn, hipDeviceSynchronize());
+            const int64_t cap = pos + pos / 4;
+            nn->cap_xp = 0;
+            if (!realloc_dev(&nn->Xp, sizeof(uint16_t) * kNnFeatures * (size_t)cap))
+                return ctx_fail(nn->ctx, SPLIT_E_NOMEM, "surrogate: packed feature buffer failed");
+            nn->cap_xp = cap;
+        }
+        NN_TRY(nn, nn_launch_features(in, tours, T, n, nn->musd, nn->Q, nn->L, nn->Xp, true,
+                                      nn->err, st));
         hipEvent_t stop = nullptr;
         s = timing_begin(nn, st, &stop);
         if (s != SPLIT_OK) return s;
-        NN_TRY(nn, nn_launch_fwd_fused(nn->X, nn->w, nn->P, T, n, nn->zpart, st));
+        NN_TRY(nn, nn_launch_fwd_fused(nn->Xp, nn->w, nn->P, T, n, nn->zpart, st));
         if (stop) NN_TRY(nn, hipEventRecord(stop, st));
         NN_TRY(nn, nn_launch_head_pool(nn->zpart, T, n, nn->P, nn->z, nn->a, nn->y, pred,
                                        nn->shift, nn->scale, st));
         return SPLIT_OK;
     }
+    NN_TRY(nn, nn_launch_features(in, tours, T, n, nn->musd, nn->Q, nn->L, nn->X, false, nn->err,
+                                  st));
     NN_TRY(nn, nn_launch_conv(kNnCi0, 0, nn->X, nn->w.f[0], nn->P + nn_off_b(0), nullptr, nn->H[0],
                               T, n, st));
     for (int l = 1; l < 4; ++l)
@@ -366,7 +380,7 @@ void free_nn(split_nn *nn)
         if (nn->w.g[l]) (void)hipFree(nn->w.g[l]);
         if (nn->H[l]) (void)hipFree(nn->H[l]);
     }
-    for (uint16_t *p : {nn->X, nn->dP[0], nn->dP[1]})
+    for (uint16_t *p : {nn->X, nn->Xp, nn->dP[0], nn->dP[1]})
         if (p) (void)hipFree(p);
     for (int32_t *p : {nn->err, nn->btours, nn->perm, nn->sidx, nn->stours, nn->ecost})
         if (p) (void)hipFree(p);

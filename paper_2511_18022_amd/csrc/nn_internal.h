@@ -55,14 +55,16 @@ struct NnSelect {
 
 hipError_t nn_launch_dstats(const int16_t *demand, int64_t ld, int64_t S, int32_t N, double *musd,
                             hipStream_t st);
+// the 8 bf16 features of every position: packed [T][n][8] for prediction, else the padded
+// training layout [T][n + 4][32] (rows 0, 1, n + 2, n + 3 and channels 8..31 left untouched)
 hipError_t nn_launch_features(const NnInstance &in, const int32_t *tours, int32_t T, int32_t n,
-                              const double *musd, int32_t Q, double L, uint16_t *X, int32_t *err,
-                              hipStream_t st);
+                              const double *musd, int32_t Q, double L, uint16_t *X, bool packed,
+                              int32_t *err, hipStream_t st);
 hipError_t nn_launch_conv(int ci, int mode, const uint16_t *X, const uint16_t *Wt,
                           const float *bias, const uint16_t *mask, uint16_t *Y, int32_t T,
                           int32_t n, hipStream_t st);
 // prediction only: the four conv layers per tile in LDS, pooled into per-tile channel sums
-// (zpart [T][tiles][128]); then the pooled mean and the head
+// (zpart [T][tiles][128]) from the packed features X [T][n][8]; then the pooled mean and the head
 int32_t nn_fused_tiles(int32_t n);
 hipError_t nn_launch_fwd_fused(const uint16_t *X, const NnWeights &w, const float *P, int32_t T,
                                int32_t n, float *zpart, hipStream_t st);

@@ -102,7 +102,8 @@ __device__ __forceinline__ long long nn_dist(const NnInstance &in, int u, int v)
 __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const int32_t *tours,
                                                           int32_t T, int32_t n,
                                                           const double *musd, int32_t Q, double L,
-                                                          uint16_t *X, int32_t *err)
+                                                          uint16_t *X, int32_t packed,
+                                                          int32_t *err)
 {
     const long long m = (long long)blockIdx.x * 256 + threadIdx.x;
     if (m >= (long long)T * n) return;
@@ -136,6 +137,10 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
     u16x8 v;
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = bf16_bits_f64(f[k]);
+    if (packed) {  // prediction input: [T][n][8], no padding rows or channels
+        *reinterpret_cast<u16x8 *>(X + m * kNnFeatures) = v;
+        return;
+    }
     u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
     u16x8 *dst = reinterpret_cast<u16x8 *>(X + ((long long)t * (n + 4) + j + 2) * kNnCi0);
     dst[0] = v;
@@ -414,13 +419,13 @@ void nn_fwd_fused_kernel(const uint16_t *X, NnWeights w, const float *P, int32_t
     FuseRing ring;
 #pragma unroll
     for (int d = 0; d < D; ++d) fuse_frag<kFuseK1>(w.g[0], cp, d, ring.b0[d], ring.b1[d]);
-    // input rows: position j0 - 8 + r (zero outside the tour), the 8 features (16 bytes; the
-    // zero channels of the input are not needed with layer 1's packed K)
+    // input rows: position j0 - 8 + r (zero outside the tour), its 8 features from the packed
+    // [T][n][8] input (16 bytes)
     for (int r = tid; r < kFuseRows; r += kFuseThreads) {
         const int pos = j0 - 8 + r;
         u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         if (pos >= 0 && pos < n)
-            v = *reinterpret_cast<const u16x8 *>(X + ((long long)t * (n + 4) + pos + 2) * kNnCi0);
+            v = *reinterpret_cast<const u16x8 *>(X + ((long long)t * n + pos) * kNnFeatures);
         *reinterpret_cast<u16x8 *>(xs + r * kFuseStrideX) = v;
     }
     fused_layer<kNnCi0, kFuseMT, 0, kNnWidth, false>(xs, ha, w.g[0], w.g[1], P + nn_off_b(0),
@@ -988,11 +993,11 @@ hipError_t nn_launch_dstats(const int16_t *demand, int64_t ld, int64_t S, int32_
 }
 
 hipError_t nn_launch_features(const NnInstance &in, const int32_t *tours, int32_t T, int32_t n,
-                              const double *musd, int32_t Q, double L, uint16_t *X, int32_t *err,
-                              hipStream_t st)
+                              const double *musd, int32_t Q, double L, uint16_t *X, bool packed,
+                              int32_t *err, hipStream_t st)
 {
     hipLaunchKernelGGL(nn_features_kernel, dim3(grid_of((long long)T * n, 256)), dim3(256), 0, st,
-                       in, tours, T, n, musd, Q, L, X, err);
+                       in, tours, T, n, musd, Q, L, X, (int32_t)packed, err);
     return hipGetLastError();
 }
 
