@@ -316,6 +316,27 @@ def test_fused_prediction_across_tile_boundaries(sg, n):
     ctx.close()
 
 
+def test_prediction_and_training_interleave_across_tour_lengths(sg, env):
+    # prediction reads its own packed features; training its padded activation layout, cleared
+    # per tour length. Alternating them over different lengths must change neither result.
+    net = make_net(sg, env, seed=4)
+    ta = env["dtours"]
+    tb = torch.from_numpy(np.stack([gen.tour(21, N, 17, variant=v) for v in range(1, 5)])).cuda()
+    tc = torch.from_numpy(np.stack([gen.tour(21, N, N, variant=v) for v in range(1, 4)])).cuda()
+    lb = torch.linspace(900.0, 1100.0, tb.shape[0], dtype=torch.float32).cuda()
+    p1 = net.predict(ta).cpu().numpy()
+    g1, l1 = net.gradient(tb, lb)
+    pc = net.predict(tc).cpu().numpy()
+    p2 = net.predict(ta).cpu().numpy()
+    g2, l2 = net.gradient(tb, lb)
+    ga, _ = net.gradient(ta, torch.from_numpy(p1).cuda())
+    p3 = net.predict(ta).cpu().numpy()
+    assert np.array_equal(p1, p2) and np.array_equal(p1, p3)
+    assert np.array_equal(np.asarray(g1), np.asarray(g2)) and l1 == l2
+    assert np.all(np.isfinite(pc)) and np.all(np.isfinite(np.asarray(ga)))
+    net.close()
+
+
 def test_shortlist_is_topk_of_predict(sg, env):
     net = make_net(sg, env, seed=2)
     cands = np.stack([gen.tour(45, N, NL, variant=v) for v in range(1, 301)])
