@@ -280,6 +280,8 @@ constexpr int kFuseStrideH = kNnWidth + 8;  // bf16 per hidden row (16 bytes of 
 static_assert(kFuseTP % 16 == 0, "the last layer covers the tile in whole m-tiles");
 static_assert(kNnFeatures == 8 && kNnTaps * kNnFeatures <= kFuseK1,
               "a tap's features are one 16-byte fragment; the taps fit layer 1's packed K");
+static_assert(kFuseDepth >= 1 && kFuseDepth <= kFuseK1 / 32,
+              "the prologue fills the ring from layer 1's K blocks alone");
 
 // K of a layer with CI input channels in the fused kernel (layer 1 packs its 8 features)
 __host__ __device__ constexpr int fuse_k(int ci) { return ci == kNnCi0 ? kFuseK1 : kNnTaps * ci; }
