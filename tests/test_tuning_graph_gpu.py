@@ -221,3 +221,36 @@ def test_graphs_reject_the_two_kernel_ablation(sg, batch):
         ctx.graph(max_T=2, max_total_n=2000, demand=dem, Q=b.Q)
     assert ei.value.status == sg.SPLIT_E_INVAL
     ctx.close()
+
+
+def test_graph_at_full_size_in_the_timed_configuration(sg):
+    # one 1000-customer tour over 2^20 copula scenarios, replayed from a captured graph as the
+    # throughput line times it (automatic form choice, cost viewed as one row): every cost of
+    # every replay against the eager evaluation, and a sample of scenarios against the oracle
+    w = gen.make_workload("copula-n1000", threads=ORACLE_THREADS)
+    ctx = fresh_ctx(sg, w.xy)
+    ctx.set_form("auto")
+    dem = torch.from_numpy(w.demand).cuda()
+    eager, est = ctx.eval(w.tour, dem, w.Q)
+    exp = eager.cpu().numpy()
+    cost = torch.empty(w.S, dtype=torch.int32, device="cuda")
+    g = ctx.graph(1, len(w.tour), dem, w.Q, cost=cost.view(1, -1))
+    for rep in range(3):
+        cost.fill_(-1)
+        print(f"[graph] copula-n1000 S={w.S} replay {rep}", flush=True)
+        got = g.launch([w.tour])
+        gstats, gstatus = g.stats()
+        torch.cuda.synchronize()
+        assert np.array_equal(got[0].cpu().numpy(), exp), f"replay {rep}"
+        assert gstatus == [0]
+        assert (gstats[0].sum, gstats[0].var) == (est.sum, est.var)
+        # eager work between replays, on the same stream
+        ctx.eval(w.tour[:500], dem, w.Q)
+    g.close()
+    idx = np.arange(0, w.S, 97)
+    sub = np.ascontiguousarray(w.demand[:, idx])
+    d = oracle.dist_matrix(w.xy)
+    assert np.array_equal(exp[idx], oracle.split(w.tour, d, sub, w.Q, threads=ORACLE_THREADS))
+    assert est.sum == int(exp.astype(np.int64).sum())
+    ctx.close()
+
