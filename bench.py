@@ -161,13 +161,24 @@ def cpu_baseline(tours, d, demand, Q, S, threads: int, got_cost, target_cpu_s: f
     for t in tours:
         oracle.split(t, d, dem1, Q, threads=1)
     el1 = time.perf_counter() - t0
+    # the strong CPU baseline: the linear-time Split (monotone deque) on the same sample and
+    # threads, its costs also compared with the GPU's
+    t0 = time.perf_counter()
+    outs_d = [oracle.split_deque(t, d, dem, Q, threads=threads) for t in tours]
+    eld = time.perf_counter() - t0
+    parity_d = all(bool(np.array_equal(got_cost[k][:sample], o)) for k, o in enumerate(outs_d))
     return {"value": evals / el, "unit": "scenario-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} of {S} scenarios of {what}, {threads} threads, "
                       f"{el:.2f} s wall",
             "parity_vs_gpu_on_sample": parity,
             "single_thread": {"value": sample1 * len(tours) / el1, "unit": "scenario-evals/s",
                               "sample": f"first {sample1} scenarios of {what}, 1 thread, "
-                                        f"{el1:.2f} s"}}
+                                        f"{el1:.2f} s"},
+            "strong": {"value": evals / eld, "unit": "scenario-evals/s", "cores": threads,
+                       "kind": "linear-time Split (monotone deque, Vidal 2016), C, threads over "
+                               "scenario ranges",
+                       "sample": f"the same {sample} scenarios, {eld:.2f} s wall",
+                       "parity_vs_gpu_on_sample": parity_d}}
 
 
 def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):

@@ -2,7 +2,9 @@
 
 Plain, slow and obviously correct: ``oracle.c`` follows the paper's Eq. (1) (Section 3)
 scenario by scenario, plus Eq. (2) masks and Eq. (3) as a cross-check, exact rounded
-Euclidean distances and exact sample-average moments. Only ``tests/``,
+Euclidean distances and exact sample-average moments. It also holds the linear-time
+(monotone-deque) Split, a strong CPU baseline that the benchmark times and the tests check
+against Eq. (1). Only ``tests/``,
 the smoke check and the benchmark's CPU-baseline leg may import this package.
 It imports nothing from the GPU library, and the GPU library imports nothing from it.
 """
@@ -67,8 +69,9 @@ def _bind(lib):
         lib.or_mask.argtypes = [P, i32, i32, P]
         lib.or_split_masked.argtypes = [P, i32, P, i32, P, P]
         lib.or_moments.argtypes = [P, i64, P, P, P, P, P]
+        lib.or_split_deque.argtypes = [P, i32, P, i32, P, i64, i64, i32, P, ctypes.c_int]
         for f in (lib.or_dist_from_coords, lib.or_split, lib.or_mask, lib.or_split_masked,
-                  lib.or_moments):
+                  lib.or_moments, lib.or_split_deque):
             f.restype = ctypes.c_int
     return lib
 
@@ -127,6 +130,26 @@ def split(tour, d, demand, Q, S=None, threads=1, return_work=False, lib=None):
     if rc != OK:
         raise OracleError(rc, "split")
     return (cost, int(work.value)) if return_work else cost
+
+
+def split_deque(tour, d, demand, Q, S=None, threads=1, lib=None):
+    """The linear-time Split (monotone deque of predecessors), scenario by scenario: the
+    strong CPU baseline for timing. Same arguments, result and errors as split()."""
+    tour = np.ascontiguousarray(tour, dtype=np.int32)
+    d = np.ascontiguousarray(d, dtype=np.int32)
+    demand = np.asarray(demand)
+    if demand.dtype != np.int16 or demand.ndim != 2 or not demand.flags.c_contiguous:
+        raise ValueError("demand must be a C-contiguous int16 [N, ld] array")
+    N, ld = demand.shape
+    S = ld if S is None else int(S)
+    if d.shape != (N + 1, N + 1):
+        raise ValueError("distance matrix must be (N+1) x (N+1)")
+    cost = np.zeros(max(S, 1), dtype=np.int32)
+    rc = _load(lib).or_split_deque(_p(tour), len(tour), _p(d), N, _p(demand), S, ld, int(Q),
+                                   _p(cost), int(threads))
+    if rc != OK:
+        raise OracleError(rc, "split_deque")
+    return cost
 
 
 def mask(q_pos, Q, lib=None) -> np.ndarray:

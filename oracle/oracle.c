@@ -316,3 +316,160 @@ int or_moments(const int32_t *cost, int64_t S, int64_t *sum_out, uint64_t *sumsq
     }
     return OR_OK;
 }
+
+/*
+ * Strong CPU baseline (a timing reference, not a correctness reference): the linear-time
+ * Split for an unlimited fleet (Vidal, "Technical note: Split algorithm in O(n) for the
+ * capacitated vehicle routing problem", Computers & Operations Research 69, 2016), one
+ * scenario at a time, threads over contiguous scenario ranges.
+ *
+ * With A[k] = sum of the tour arcs from position 1 to position k (A[1] = 0), the route of
+ * positions p+1..i costs d[0][s_{p+1}] + A[i] - A[p+1] + d[s_i][0], so
+ *     f(i) = A[i] + d[s_i][0] + min over the feasible p of  key(p),
+ *     key(p) = f(p) + d[0][s_{p+1}] - A[p+1].
+ * The feasible p of state i form the window [start(i), i-1] of Eq. (2), whose start never
+ * decreases with i (demands are >= 0). A deque of predecessors kept increasing in key gives
+ * each window minimum at its front: a predecessor leaves at the front once the window start
+ * passes it, and at the back once a later one has a key no larger. Each p enters and leaves
+ * once: O(n) per scenario. The tests check it against or_split on every scenario.
+ */
+typedef struct {
+    int32_t n;
+    const int32_t *tour;
+    const int64_t *A, *out0, *back0;
+    const int16_t *dem;
+    int64_t ld, s_begin, s_end;
+    int32_t Q;
+    int32_t *cost_out;
+    int rc;
+} or_deque_job;
+
+/* One scenario: q[k] is the demand at tour position k+1; P, key and dq are scratch of n+1. */
+static int deque_one(int32_t n, const int64_t *A, const int64_t *out0, const int64_t *back0,
+                     const int16_t *q, int32_t Q, int64_t *P, int64_t *key, int32_t *dq,
+                     int64_t *cost)
+{
+    P[0] = 0;
+    for (int32_t k = 1; k <= n; ++k) {
+        if (q[k - 1] < 0 || q[k - 1] > Q) return OR_E_DEMAND;
+        P[k] = P[k - 1] + q[k - 1];
+    }
+    int32_t head = 0, tail = 0, start = 0;
+    int64_t f = 0;
+    key[0] = out0[0] - A[1]; /* f(0) = 0 */
+    dq[tail++] = 0;
+    for (int32_t i = 1; i <= n; ++i) {
+        while (P[i] - P[start] > Q) ++start;
+        while (head < tail && dq[head] < start) ++head;
+        if (head == tail) return OR_E_DEMAND; /* not reached once q_i <= Q: p = i-1 is feasible */
+        f = key[dq[head]] + A[i] + back0[i];
+        if (i < n) {
+            key[i] = f + out0[i] - A[i + 1];
+            while (head < tail && key[dq[tail - 1]] >= key[i]) --tail;
+            dq[tail++] = i;
+        }
+    }
+    *cost = f;
+    return OR_OK;
+}
+
+#define OR_DEQUE_BLOCK 32 /* scenarios whose demand rows are copied out together */
+
+static void *deque_worker(void *arg)
+{
+    or_deque_job *jb = (or_deque_job *)arg;
+    const int32_t n = jb->n;
+    int64_t *P = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int32_t *dq = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    /* the block's demands, scenario-major: qb[b * n + k] = demand of scenario s0 + b at tour
+       position k + 1 (one pass over each demand row, then contiguous reads per scenario) */
+    int16_t *qb = (int16_t *)malloc(sizeof(int16_t) * (size_t)n * OR_DEQUE_BLOCK);
+    jb->rc = (P && key && dq && qb) ? OR_OK : OR_E_NOMEM;
+    for (int64_t s0 = jb->s_begin; s0 < jb->s_end && jb->rc == OR_OK; s0 += OR_DEQUE_BLOCK) {
+        const int nb = (int)(jb->s_end - s0 < OR_DEQUE_BLOCK ? jb->s_end - s0 : OR_DEQUE_BLOCK);
+        for (int32_t k = 0; k < n; ++k) {
+            const int16_t *row = jb->dem + (int64_t)(jb->tour[k] - 1) * jb->ld + s0;
+            for (int b = 0; b < nb; ++b) qb[(size_t)b * n + k] = row[b];
+        }
+        for (int b = 0; b < nb; ++b) {
+            int64_t c = 0;
+            int rc = deque_one(n, jb->A, jb->out0, jb->back0, qb + (size_t)b * n, jb->Q, P, key,
+                               dq, &c);
+            if (rc == OR_OK && c > INT32_MAX) rc = OR_E_INVAL;
+            if (rc != OR_OK) {
+                jb->rc = rc;
+                break;
+            }
+            jb->cost_out[s0 + b] = (int32_t)c;
+        }
+    }
+    free(P);
+    free(key);
+    free(dq);
+    free(qb);
+    return NULL;
+}
+
+/* The same contract as or_split (without the work count), computed by the linear Split. */
+int or_split_deque(const int32_t *tour, int32_t n, const int32_t *d, int32_t N,
+                   const int16_t *demand, int64_t S, int64_t ld, int32_t Q, int32_t *cost_out,
+                   int nthreads)
+{
+    if (!tour || !d || !demand || !cost_out || n < 1 || N < 1 || n > N || S < 1 || ld < S ||
+        Q < 1)
+        return OR_E_INVAL;
+    int rc = check_tour(tour, n, N);
+    if (rc != OR_OK) return rc;
+    const int64_t V = (int64_t)N + 1;
+    /* tour arrays shared by every scenario: A[1..n], out0[0..n-1], back0[1..n] */
+    int64_t *A = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *out0 = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *back0 = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!A || !out0 || !back0) {
+        free(A);
+        free(out0);
+        free(back0);
+        return OR_E_NOMEM;
+    }
+    A[0] = 0;
+    A[1] = 0;
+    for (int32_t k = 2; k <= n; ++k) A[k] = A[k - 1] + DIST(tour[k - 2], tour[k - 1]);
+    for (int32_t p = 0; p < n; ++p) out0[p] = DIST(0, tour[p]);
+    back0[0] = 0;
+    for (int32_t i = 1; i <= n; ++i) back0[i] = DIST(tour[i - 1], 0);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((int64_t)nthreads > S) nthreads = (int)S;
+    or_deque_job jobs[256];
+    pthread_t th[256];
+    int64_t per = (S + nthreads - 1) / nthreads;
+    int started = 0;
+    rc = OR_OK;
+    for (int t = 0; t < nthreads; ++t) {
+        or_deque_job *jb = &jobs[t];
+        jb->n = n; jb->tour = tour; jb->A = A; jb->out0 = out0; jb->back0 = back0;
+        jb->dem = demand; jb->ld = ld; jb->Q = Q; jb->cost_out = cost_out; jb->rc = OR_OK;
+        jb->s_begin = (int64_t)t * per;
+        jb->s_end = jb->s_begin + per < S ? jb->s_begin + per : S;
+        if (jb->s_begin >= jb->s_end) break;
+        if (nthreads == 1) {
+            deque_worker(jb);
+            started = 1;
+            break;
+        }
+        if (pthread_create(&th[t], NULL, deque_worker, jb) != 0) {
+            rc = OR_E_NOMEM;
+            break;
+        }
+        ++started;
+    }
+    if (nthreads > 1)
+        for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < started; ++t)
+        if (jobs[t].rc != OR_OK && rc == OR_OK) rc = jobs[t].rc;
+    free(A);
+    free(out0);
+    free(back0);
+    return rc;
+}
