@@ -130,6 +130,20 @@ def window_work(dem, tours, Q: int, chunk: int = 16384) -> int:
     return total
 
 
+def host_cpu() -> dict:
+    """The host the CPU baselines ran on: CPU model (from /proc/cpuinfo) and logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(tours, d, demand, Q, S, threads: int, got_cost, target_cpu_s: float = 20.0):
     """The oracle as it stands, on the host cores, over a bounded sample of the scenarios (the
     first `sample` scenarios of every tour, about target_cpu_s of single-core work). Its output
@@ -178,7 +192,8 @@ def cpu_baseline(tours, d, demand, Q, S, threads: int, got_cost, target_cpu_s: f
                        "kind": "linear-time Split (monotone deque, Vidal 2016), C, threads over "
                                "scenario ranges",
                        "sample": f"the same {sample} scenarios, {eld:.2f} s wall",
-                       "parity_vs_gpu_on_sample": parity_d}}
+                       "parity_vs_gpu_on_sample": parity_d},
+            "host": host_cpu()}
 
 
 def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
@@ -357,7 +372,7 @@ def run_screen(args, threads):
                                "kind": "oracle",
                                "sample": f"exact evaluation of the first {k} candidates at "
                                          f"S={w.S}, {threads} threads, {el:.1f} s wall",
-                               "parity_vs_gpu_on_sample": bool(ok)}
+                               "parity_vs_gpu_on_sample": bool(ok), "host": host_cpu()}
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
