@@ -13,6 +13,8 @@
 // + e], B[k (l/16)*8 + e][col l % 16], and D[row (l/16)*4 + i][col l % 16], e < 8, i < 4.
 //
 // Every reduction runs in a fixed order, so results are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "nn_internal.h"
 
 namespace splitgpu {
@@ -283,6 +285,17 @@ static_assert(kNnFeatures == 8 && kNnTaps * kNnFeatures <= kFuseK1,
 static_assert(kFuseDepth >= 1 && kFuseDepth <= kFuseK1 / 32,
               "the prologue fills the ring from layer 1's K blocks alone");
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to bf16 bits in one instruction (round to nearest, ties to even, as
+// bf16_bits_f32): lo in bits 0..15, hi in bits 16..31.
+__device__ __forceinline__ uint32_t bf16x2_bits(float lo, float hi)
+{
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
 // K of a layer with CI input channels in the fused kernel (layer 1 packs its 8 features)
 __host__ __device__ constexpr int fuse_k(int ci) { return ci == kNnCi0 ? kFuseK1 : kNnTaps * ci; }
 
@@ -358,26 +371,46 @@ __device__ __forceinline__ void fused_part(const uint16_t *in, uint16_t *out, co
         // would push the wave past the budget of two waves per SIMD and into scratch
         __builtin_amdgcn_sched_barrier(0);
     }
+    // bias, ReLU, rows outside the tour zeroed (MASK; a layer whose rows all lie inside the
+    // tour, the uniform common case, needs no row test), then bf16 two rows at a time
+    auto epilogue = [&](auto mask_tag) {
+        constexpr bool MASK = decltype(mask_tag)::value;
 #pragma unroll
-    for (int mt = 0; mt < MC; ++mt) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = mt * 16 + kq * 4 + i;
-            const int pos = pos0 + row;
-            const bool inside = pos >= 0 && pos < n;
+        for (int mt = 0; mt < MC; ++mt) {
+            const int r0 = mt * 16 + kq * 4;  // this lane's 4 rows: r0 .. r0 + 3
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int co = (2 * cp + h) * 16 + r16;
-                float v = acc[mt][h][i] + bias[co];
-                v = v > 0.f && inside ? v : 0.f;
-                const uint16_t bv = bf16_bits_f32(v);
-                if (POOL)
-                    sum[h] += bf16_to_f32(bv);
-                else
-                    out[row * kFuseStrideH + co] = bv;
+                const float b = bias[co];
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = fmaxf(acc[mt][h][i] + b, 0.f);
+                    if (MASK) {
+                        const int pos = pos0 + r0 + i;
+                        v[i] = pos >= 0 && pos < n ? v[i] : 0.f;
+                    }
+                }
+                const uint32_t p01 = bf16x2_bits(v[0], v[1]), p23 = bf16x2_bits(v[2], v[3]);
+                if (POOL) {
+                    sum[h] += __uint_as_float(p01 << 16);
+                    sum[h] += __uint_as_float(p01 & 0xFFFF0000u);
+                    sum[h] += __uint_as_float(p23 << 16);
+                    sum[h] += __uint_as_float(p23 & 0xFFFF0000u);
+                } else {
+                    uint16_t *o = out + r0 * kFuseStrideH + co;
+                    o[0] = (uint16_t)p01;
+                    o[kFuseStrideH] = (uint16_t)(p01 >> 16);
+                    o[2 * kFuseStrideH] = (uint16_t)p23;
+                    o[3 * kFuseStrideH] = (uint16_t)(p23 >> 16);
+                }
             }
         }
-    }
+    };
+    if (pos0 >= 0 && pos0 + MC * 16 <= n)
+        epilogue(std::false_type{});
+    else
+        epilogue(std::true_type{});
 }
 
 // One layer over MT m-tiles (see fused_part). With POOL the tile's channel sums go to
