@@ -50,6 +50,17 @@ __device__ __forceinline__ uint16_t bf16_bits_f64(double x)
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// fp32 -> bf16 bits by the hardware conversion (round to nearest, ties to even: the same bits
+// as bf16_bits_f32 for every finite value) in one instruction
+__device__ __forceinline__ uint16_t bf16_bits_hw(float x)
+{
+    const f32x2_t v = {x, 0.f};
+    return (uint16_t)__builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
 // ------------------------------------------------------------------------- demand statistics
 
 // One workgroup per customer: exact integer sums of q and q^2 over the S scenarios, then the
@@ -231,14 +242,24 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
         __syncthreads();
     }
     if (m0 >= M) return;
-    // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile
+    // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile.
+    // Row mb + off (off <= 51) is position jb + off of tour tb, carried into the next tours
+    // past their ends: one division per lane.
+    const long long mb = m0 + (lane >> 4) * 4;
+    const long long tb = mb / n;
+    const int jb = (int)(mb - tb * n);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const long long m = m0 + mt * 16 + (lane >> 4) * 4 + i;
-            if (m >= M) continue;
-            const long long t = m / n, j = m - t * n;
+            const int off = mt * 16 + i;
+            if (mb + off >= M) continue;
+            long long t = tb;
+            int j = jb + off;
+            while (j >= n) {
+                j -= n;
+                ++t;
+            }
             const long long base = (t * (n + 4) + j + 2) * kNnWidth;
 #pragma unroll
             for (int nt = 0; nt < 8; ++nt) {
@@ -250,7 +271,7 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
                 } else {
                     if (mask[base + co] == 0 || (mask[base + co] & 0x8000u)) v = 0.f;
                 }
-                Y[base + co] = bf16_bits_f32(v);
+                Y[base + co] = bf16_bits_hw(v);
             }
         }
 }
