@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
-_LIB = os.path.join(_HERE, "libsplitgen.so")
+# SPLIT_GEN_LIB names another build of gen.c (the sanitizer test's instrumented copy)
+_LIB = os.environ.get("SPLIT_GEN_LIB") or os.path.join(_HERE, "libsplitgen.so")
 _lib = None
 
 

@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SPLIT_ORACLE_LIB names another build of oracle.c (the sanitizer test's instrumented copy)
+_LIB = os.environ.get("SPLIT_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 _libs = {}
 
