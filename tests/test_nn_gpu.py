@@ -10,8 +10,9 @@ factor and about 1% of the stored values flip per layer; with all-positive weigh
 cancels and flips are rare. So:
   - all-positive weights: outputs to 2e-5 (1 + |y|), every gradient tensor to 2e-3 of its norm,
     at tour lengths 6 (boundary rows dominate) and 40 (measured: 3e-5 and 2.5e-4 at most);
-  - random weights: outputs to 1e-3 (1 + |y|), gradient tensors to 1e-2 of their norm (measured:
-    3e-4 and 1.3e-3 at most; W1 sits behind three backward convolutions of flipped roundings);
+  - random weights: outputs to 1e-3 (1 + |y|), every gradient tensor to 3e-3 of its norm
+    (measured: 3e-4 and 1.3e-3 at most, the largest on W1, which sits behind three backward
+    convolutions of flipped roundings);
   - Adam's update to fp32 rounding.
 """
 import os
@@ -177,7 +178,7 @@ def test_gradient_matches_reference_with_random_weights(sg, env):
     # bfloat16 roundings flipped by fp32 summation under heavy cancellation compound over the
     # three backward convolutions in front of W1
     for name, (e, _) in errs.items():
-        assert e <= 1e-2, name
+        assert e <= 3e-3, name
     net.close()
 
 
