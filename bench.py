@@ -424,12 +424,21 @@ def run_search(args, threads):
         f"predicted, {assisted['evaluated']} exact, {assisted['start_mean']:.2f} -> "
         f"{assisted['best_mean']:.2f}")
     hdem = torch.from_numpy(held).cuda()
-    oos = {}
+    oos, saa = {}, {}
     for name, t in (("start", base), ("exact_only", exact["best_tour"]),
                     ("surrogate", assisted["best_tour"])):
         _, st = ctx.eval(t, hdem, w.Q)
+        _, st_in = ctx.eval(t, dem, w.Q)
         oos[name] = st.mean
-    log(f"out-of-sample means: {oos}")
+        # sample-average check (the appendix's rate of convergence): in-sample and held-out
+        # means of one tour differ by N(0, var_in / S_in + var_out / S_out) when the tour was
+        # not chosen on the in-sample scenarios; a searched tour's in-sample mean is optimistic
+        se = float(np.sqrt(st_in.var / S_in + st.var / S_out))
+        saa[name] = {"in_sample": st_in.mean, "held_out": st.mean, "se": se,
+                     "gap_in_se": (st_in.mean - st.mean) / se}
+    saa["start_within_4se"] = abs(saa["start"]["gap_in_se"]) <= 4.0
+    log(f"out-of-sample means: {oos}; start tour in-sample minus held-out = "
+        f"{saa['start']['gap_in_se']:.2f} standard errors")
 
     def summary(r):
         return {k: r[k] for k in ("iterations", "evaluated", "predicted", "improvements",
@@ -450,6 +459,7 @@ def run_search(args, threads):
         "exact_only": summary(exact),
         "surrogate": summary(assisted),
         "out_of_sample": {"scenarios": S_out, **oos},
+        "saa_check": saa,
         "config": {"workload": "search", "N": w.N, "S": S_in, "Q": w.Q, "budget_s": args.budget,
                    "batch": args.search_batch, "pool": args.search_pool,
                    "surrogate_prep_seconds": prep_s, "train_tours": len(w.train),
@@ -460,6 +470,96 @@ def run_search(args, threads):
     }
     print(json.dumps(out), flush=True)
     nn.close()
+    ctx.close()
+
+
+SCALING_S = (10_000, 65_536, 100_000, 131_072, 262_144, 524_288, 1_000_000, 1 << 20)
+
+
+def run_scaling(args, threads):
+    """Runtime against the number of scenarios for one giant tour (n = 1000, copula demands):
+    the paper's first experiment (Section 4.1, Fig. 3) on one GPU, with the CPU oracle on one
+    thread and on every host core and the linear-time CPU Split beside every point. The
+    scenario sets are the first S columns of the 2^20-scenario matrix (the generator is keyed by
+    scenario), each launch reading a column slice of the resident matrix."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_2511_18022_amd as sg
+    Smax = max(SCALING_S)
+    t0 = time.perf_counter()
+    w = gen.make_workload("copula-n1000", S=Smax, threads=threads)
+    log(f"generated copula-n1000 at S={Smax} in {time.perf_counter() - t0:.1f}s")
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    d = oracle.dist_matrix(w.xy)
+    cost = torch.empty(Smax, dtype=torch.int32, device="cuda")
+    points = []
+    for S in SCALING_S:
+        sl = dem[:, :S]
+
+        def step():
+            ctx.eval(w.tour, sl, w.Q, cost=cost, sync=False)
+        ms, kern_ms, kname, launches, kern_med = timed_steps(ctx, step, ctx.batch_stats,
+                                                             args.steps, args.warmup)
+        stats, _ = ctx.batch_stats()
+        M = window_work(sl, [w.tour], w.Q)
+        ops = M / 2 + 4 * w.n * S
+        alu = ops / (kern_ms * 1e-3) / 1e12
+        hbm = (2 * w.n + 4) * S / (kern_ms * 1e-3) / 1e9
+        pt = {"S": S, "kernel": kname, "kernel_ms": kern_ms, "kernel_median_ms": kern_med,
+              "ms_per_step": ms, "evals_per_s": S / (ms * 1e-3),
+              "kernel_ns_per_scenario": kern_ms * 1e6 / S,
+              "alu_frac": alu / ALU_PEAK_TOPS, "hbm_frac": hbm / HBM_PEAK_GBS,
+              "fallback_scenarios": stats[0].n_fallback}
+        # CPU baselines on the same columns (layout [N][S]: the oracle strides over the whole
+        # S-wide rows as the GPU does): time a bounded prefix of scenarios, report evals/s and
+        # the time the whole set takes at that rate
+        got = cost[:S].cpu().numpy()
+        sub = np.ascontiguousarray(w.demand[:, :S])
+        for key, fn, thr, budget in (("cpu_1t", oracle.split, 1, 2.0),
+                                     ("cpu_mt", oracle.split, threads, 2.0),
+                                     ("cpu_deque_mt", oracle.split_deque, threads, 1.0)):
+            k = min(S, 1024)
+            while True:
+                t1 = time.perf_counter()
+                out = fn(w.tour, d, sub, w.Q, S=k, threads=thr)
+                el = time.perf_counter() - t1
+                if el >= budget / 4 or k == S:
+                    break
+                k = min(S, k * 4)
+            assert np.array_equal(out, got[:k]), f"{key}: CPU and GPU costs differ at S={S}"
+            rate = k / el
+            pt[key] = {"evals_per_s": rate, "scenarios_timed": k, "threads": thr,
+                       "seconds_for_S": S / rate}
+        pt["speedup_vs_cpu_1t"] = pt["evals_per_s"] / pt["cpu_1t"]["evals_per_s"]
+        pt["speedup_vs_cpu_mt"] = pt["evals_per_s"] / pt["cpu_mt"]["evals_per_s"]
+        pt["speedup_vs_cpu_deque_mt"] = pt["evals_per_s"] / pt["cpu_deque_mt"]["evals_per_s"]
+        log(f"S={S}: kernel {kern_ms:.4f} ms ({pt['kernel_ns_per_scenario']:.3f} ns/scenario), "
+            f"step {ms:.4f} ms, ALU {pt['alu_frac']:.3f}, x{pt['speedup_vs_cpu_1t']:.0f} vs 1T, "
+            f"x{pt['speedup_vs_cpu_mt']:.0f} vs {threads}T")
+        points.append(pt)
+    big = points[-1]
+    out = {
+        "metric": "Split runtime against the number of scenarios (n=1000, copula demands)",
+        "value": big["evals_per_s"],
+        "unit": "scenario-evals/s at the largest S",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": big["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "scaling", "n": w.n, "Q": w.Q, "demand": COPULA_DESC,
+                   "S": list(SCALING_S), "host": host_cpu(),
+                   "paper_claim": "near-linear GPU time in the number of scenarios over 10^4-10^6 "
+                                  "(NVIDIA RTX 2080 Ti; CPU baselines on an AMD Ryzen 7 9700X, "
+                                  "1 and 8 threads)"},
+        "points": points,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 
@@ -523,6 +623,9 @@ def main():
         return
     if args.workload == "search":
         run_search(args, threads)
+        return
+    if args.workload == "scaling":
+        run_scaling(args, threads)
         return
     batch = args.workload in gen.BATCH_RECIPES
     t0 = time.perf_counter()

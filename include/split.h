@@ -17,8 +17,12 @@
  *    depot's location, so the closing arc of a route ending at customer c is d[c][0].
  *  - Unlimited fleet, no route-length limit (the optional limit the paper mentions is not used).
  *  - A context is not thread-safe: use one context per host thread / stream.
- *  - Limits: 1 <= n <= N <= SPLIT_MAX_N, 1 <= Q <= 16383, 1 <= S < 2^31 (Q is bounded so that
- *    a window's load difference, at most 2Q, fits a signed 16-bit compare).
+ *  - Limits: 1 <= n <= N <= SPLIT_MAX_N, Q >= 1 (any int32 capacity), 1 <= S < 2^31. The
+ *    scenario-per-lane kernel compares load differences in 16 bits, exact while
+ *    8 * max(q) + Q < 2^15; evaluations with Q > 16383 run in the wavefront-per-scenario form
+ *    (exact for any Q) whatever form is chosen, and single scenarios outside the bound are
+ *    handed to it. SPLIT_MAX_N is the wave kernel's LDS budget: it holds a scenario's prefix
+ *    loads and DP values (8 bytes per position) in LDS.
  */
 #ifndef SPLIT_H
 #define SPLIT_H
@@ -45,7 +49,8 @@ typedef enum {
 /* Kernel form used by split_eval (all compute identical results). */
 typedef enum {
     SPLIT_FORM_AUTO = 0, /* scenario-per-lane for large S, wavefront-per-scenario for small S */
-    SPLIT_FORM_LANE = 1, /* one scenario per lane; sliding-window minimum in LDS */
+    SPLIT_FORM_LANE = 1, /* one scenario per lane; sliding-window minimum in LDS (Q <= 16383;
+                            a larger Q runs in the wave form) */
     SPLIT_FORM_WAVE = 2, /* one scenario per wavefront; lanes over predecessors p */
     SPLIT_FORM_MASK = 3  /* ablation, the two-kernel form of Section 3: the Eq. (2) window starts
                             of every state and scenario are written to an int16 matrix in device

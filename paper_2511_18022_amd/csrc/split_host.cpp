@@ -21,6 +21,9 @@ namespace {
 
 constexpr int kStages = 8;              // pinned host slots for tour uploads
 constexpr int64_t kWaveAutoMaxS = 4096;  // SPLIT_FORM_AUTO uses the wave form up to this S
+// The lane kernel compares load differences in 16 bits, exact while 8 * max(q) + Q < 2^15;
+// evaluations with a larger capacity run in the wave form, which is exact for any Q.
+constexpr int32_t kLaneMaxQ = 16383;
 constexpr int kMaxTimingPairs = 4096;
 constexpr int kGraphSlots = 2;          // a graph's launches alternate between two host slots
 constexpr int32_t kMaxLanePerCu = 8;    // the lane kernel's LDS allows 8 workgroups per CU
@@ -363,7 +366,7 @@ split_status check_shape(split_ctx *ctx, const char *who, int64_t S, int64_t ld,
 {
     if (S < 1 || S > INT32_MAX || ld < S || ldc < S)
         return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= S < 2^31, ld >= S and ldc >= S", who);
-    if (Q < 1 || Q > 16383) return fail(ctx, SPLIT_E_INVAL, "%s: need 1 <= Q <= 16383", who);
+    if (Q < 1) return fail(ctx, SPLIT_E_INVAL, "%s: need Q >= 1", who);
     return SPLIT_OK;
 }
 
@@ -429,12 +432,14 @@ void stage_write(char *h, const StageLayout &L, const int32_t *tours, const int6
 }
 
 // Launch configuration from the tuning. T_grid bounds T; maxn and max_id bound the tours.
-Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t ld,
+Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t ld, int32_t Q,
                int32_t T_grid, int32_t maxn, int32_t max_id)
 {
     Plan p;
     p.form = tu.form;
     if (p.form == SPLIT_FORM_AUTO) p.form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
+    // past the lane kernel's 16-bit bound every scenario would be handed to the wave kernel
+    if (p.form == SPLIT_FORM_LANE && Q > kLaneMaxQ) p.form = SPLIT_FORM_WAVE;
     // the lane kernel addresses demands with 32-bit buffer offsets
     const __int128 lane_bytes = ((__int128)(max_id - 1) * ld + S) * 2;
     const bool lane_addressable = lane_bytes <= (__int128)kRowAbsent;
@@ -559,7 +564,7 @@ split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
     HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[slot], stream));
     ctx->stage_ev_used[slot] = true;
 
-    const Plan p = make_plan(ctx, ctx->tuning, S, ld, T, bi.maxn, bi.max_id);
+    const Plan p = make_plan(ctx, ctx->tuning, S, ld, Q, T, bi.maxn, bi.max_id);
     if (p.form == SPLIT_FORM_MASK && (__int128)ctx->buf.cap_pos * S > ctx->buf.cap_mask) {
         // one int16 window start per (position row, scenario)
         HIP_TRY(ctx, hipDeviceSynchronize());
@@ -878,7 +883,7 @@ split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t 
 
     split_tuning win = saved;
     double win_ms = 1e300;
-    const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0}, S, ld, T,
+    const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0}, S, ld, Q, T,
                                       bi.maxn, bi.max_id);
     if (lane_probe.form == SPLIT_FORM_LANE) {
         const int32_t per_cu[] = {0, 8, 4, 2};
@@ -1059,7 +1064,7 @@ split_status split_graph_create(split_ctx *ctx, int32_t max_T, int64_t max_total
                         (int64_t)nblk * max_T, true);
     if (st != SPLIT_OK) return bail(st);
     // any tour of the instance: lengths up to N, ids up to N
-    gr->plan = make_plan(ctx, ctx->tuning, S, ld, max_T, N, N);
+    gr->plan = make_plan(ctx, ctx->tuning, S, ld, Q, max_T, N, N);
     if (gr->plan.form == SPLIT_FORM_MASK)
         return bail(fail(ctx, SPLIT_E_INVAL, "split_graph_create: the two-kernel form is an "
                          "ablation and is not captured"));

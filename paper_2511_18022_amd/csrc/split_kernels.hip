@@ -688,7 +688,14 @@ __device__ void wave_one(const EvalArgs &a, int t, long long scen, int32_t *G, i
     const int lo = lane * chunk + 1;
     const int hi = min(lo + chunk - 1, n);
     int local = 0;
-    for (int i = lo; i <= hi; ++i) local += *(const uint16_t *)(dem + rowoff[i]);
+    uint32_t qor = 0;
+    for (int i = lo; i <= hi; ++i) {
+        const uint32_t q = *(const uint16_t *)(dem + rowoff[i]);
+        local += (int)q;
+        qor |= q;
+    }
+    // a negative int16 demand (bit 15) is rejected for any Q, also where Q admits 2^15 and more
+    const bool neg = __any((qor & 0x8000u) != 0);
     int run = wave_exclusive_sum(local);
     for (int i = lo; i <= hi; ++i) {
         run += *(const uint16_t *)(dem + rowoff[i]);
@@ -700,8 +707,8 @@ __device__ void wave_one(const EvalArgs &a, int t, long long scen, int32_t *G, i
     }
     __syncthreads();
     int s = 0;
-    bool err = false;
-    for (int i = 1; i <= n; ++i) {
+    bool err = neg;
+    for (int i = 1; i <= n && !err; ++i) {
         const int P = PP[i];
         while (P - PP[s] > Q) ++s;
         if (s == i) {
@@ -782,12 +789,14 @@ __global__ __launch_bounds__(64) void split_mask_kernel(EvalArgs a, int16_t *mas
     const char *dem = reinterpret_cast<const char *>(a.demand + scen);
     int P = 0, Ps = 0, s = 0;
     for (int i = 1; i <= n; ++i) {
-        P += *(const uint16_t *)(dem + rowoff[i]);
+        const uint32_t q = *(const uint16_t *)(dem + rowoff[i]);
+        P += (int)q;
         while (s < i && P - Ps > a.Q) {
             ++s;
             Ps += *(const uint16_t *)(dem + rowoff[s]);
         }
-        mask[(ab + i) * mask_ld + scen] = (int16_t)s;
+        // a negative int16 demand (bit 15) gets an empty window: reported as infeasible
+        mask[(ab + i) * mask_ld + scen] = (int16_t)((q & 0x8000u) ? i : s);
     }
 }
 

@@ -174,7 +174,7 @@ def test_invalid_arguments(ctx):
         (np.array([0, 2, 3], dtype=np.int32), 100, sg.SPLIT_E_TOUR),
         (np.array([1, 2, 21], dtype=np.int32), 100, sg.SPLIT_E_TOUR),
         (w.tour, 0, sg.SPLIT_E_INVAL),
-        (w.tour, 16384, sg.SPLIT_E_INVAL),
+        (w.tour, -5, sg.SPLIT_E_INVAL),
     ]:
         with pytest.raises(sg.SplitError) as ei:
             ctx.eval(tour, dem, Q)
@@ -232,6 +232,41 @@ def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi)
     # a quarter of the scenarios with small demands (long windows) in the same launch
     dem[:, : S // 4] = rng.integers(0, 40, size=(N, S // 4)).astype(np.int16)
     check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
+
+
+@pytest.mark.parametrize("form", ["auto", "lane", "wave", "mask"])
+@pytest.mark.parametrize("Q", [16384, 20000, 32767, 40000, 2**31 - 1])
+def test_capacity_beyond_16bit_lane_bound(ctx, form, Q):
+    # Eq. (2) holds for any capacity. Demands span the whole int16 range up to Q, so windows run
+    # from one customer (demands near Q) to the whole tour (Q far above every load); the
+    # evaluation leaves the lane kernel's 16-bit arithmetic for the wave form.
+    rng = np.random.default_rng(Q % 1000003)
+    N = 300
+    xy = gen.coords(17, N)
+    d = oracle.dist_matrix(xy)
+    tour = gen.tour(17, N, 250)
+    S = 2500
+    qmax = min(Q, 32767)
+    dem = rng.integers(0, qmax + 1, size=(N, S)).astype(np.int16)
+    dem[:, : S // 3] = rng.integers(0, 200, size=(N, S // 3)).astype(np.int16)
+    dem[:, S // 3: S // 2] = rng.integers(qmax // 2, qmax + 1, size=(N, S // 2 - S // 3))
+    print(f"[parity] Q={Q} form {form} N={N} n=250 S={S}", flush=True)
+    check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
+
+
+@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+def test_negative_demand_reported_at_capacity_beyond_int16(ctx, form):
+    # with Q >= 2^15 a negative int16 demand read as unsigned would fit the capacity: it must
+    # still be reported as infeasible
+    import paper_2511_18022_amd as sg
+    w = gen.make_workload("uniform-n20", S=500)
+    dem = w.demand.copy()
+    dem[int(w.tour[3]) - 1, 77] = -1
+    ctx.set_coords(w.xy)
+    ctx.set_form(form)
+    with pytest.raises(sg.SplitError) as ei:
+        ctx.eval(w.tour, torch.from_numpy(dem).cuda(), 40000)
+    assert ei.value.status == sg.SPLIT_E_DEMAND
 
 
 def test_async_calls_and_stats_get(ctx):

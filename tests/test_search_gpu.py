@@ -111,3 +111,25 @@ def test_search_argument_errors(env):
     with pytest.raises(sg.SplitError) as ei:
         sg.search(env["ctx"], bad, env["ddem"], Q, batch=4, budget_s=1.0)
     assert ei.value.status == sg.SPLIT_E_TOUR
+
+
+def test_held_out_scenarios_agree_with_the_sample_average(env):
+    # the appendix's Monte Carlo proposition on held-out scenarios: the start tour was not chosen
+    # on the in-sample scenarios, so its in-sample and held-out means differ by about one
+    # standard error sqrt(var_in / S_in + var_out / S_out); the searched tour keeps its gain out
+    # of sample
+    sg, ctx = env["sg"], env["ctx"]
+    r = sg.search(ctx, env["tour0"], env["ddem"], Q, batch=32, budget_s=60.0, max_iters=25,
+                  seed=7)
+    S_out = 200_000
+    held = torch.from_numpy(gen.demand_uniform(32, N, S_out, 0, 25)).cuda()
+    _, start_in = ctx.eval(env["tour0"], env["ddem"], Q)
+    _, start_out = ctx.eval(env["tour0"], held, Q)
+    _, best_out = ctx.eval(r["best_tour"], held, Q)
+    se = np.sqrt(start_in.var / S + start_out.var / S_out)
+    gap = (start_in.mean - start_out.mean) / se
+    print(f"[search] start in-sample {start_in.mean:.2f}, held-out {start_out.mean:.2f} "
+          f"({gap:.2f} se); searched tour held-out {best_out.mean:.2f}", flush=True)
+    assert abs(gap) <= 4.0
+    best_se = np.sqrt(best_out.var / S_out + start_out.var / S_out)
+    assert start_out.mean - best_out.mean > 4.0 * best_se
