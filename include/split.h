@@ -124,6 +124,27 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
                         void *hip_stream);
 
 /*
+ * split_eval for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same evaluation and results as
+ * split_eval, with every per-call device buffer (the staged tour, the per-position arrays, the
+ * result block, the counters and the moment partials) carved from a fixed scratch array of
+ * 192 KiB that each GPU holds for the life of the process. The call makes no device or pinned
+ * host allocation; the context, its instance and the caller's demand and cost buffers must
+ * exist beforehand. Arguments as in split_eval; `tour` is copied from pageable host memory.
+ *  stats  HOST or NULL. Non-NULL: the call waits for the evaluation and fills it. NULL: the
+ *         call only enqueues (split_stats_get does not report these calls).
+ * All calls on one GPU share its scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (other streams, other host threads, other contexts) race; order them.
+ * The context's timing and its latest-call statistics are left as they were.
+ * Errors: as split_eval; SPLIT_E_INVAL also when the context's form is SPLIT_FORM_MASK (its
+ * mask matrix needs an allocation) or a tour does not fit the scratch (never for n <= N <=
+ * SPLIT_MAX_N).
+ */
+split_status split_eval_noalloc(split_ctx *ctx, const int32_t *tour, int32_t n,
+                                const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                                int32_t *cost, split_stats *stats, void *hip_stream);
+
+/*
  * Wait for the latest split_eval on ctx and return its statistics. Returns SPLIT_E_DEMAND if
  * that call found an infeasible demand, SPLIT_E_INVAL if no call was made yet.
  */

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "SPLIT_OK", -1: "SPLIT_E_INVAL", -2: "SPLIT_E_TOUR", -3: "SPL
 # Every function declared in include/split.h.
 EXPORTED = [
     "split_ctx_create", "split_ctx_destroy", "split_last_error", "split_instance_set_coords",
-    "split_instance_set_dist", "split_eval", "split_stats_get", "split_eval_batch",
+    "split_instance_set_dist", "split_eval", "split_eval_noalloc", "split_stats_get",
+    "split_eval_batch",
     "split_batch_stats_get", "split_set_form", "split_timing_enable", "split_timing_get",
     "split_timing_reset", "split_timing_samples", "split_tuning_set", "split_tuning_get",
     "split_autotune", "split_graph_create", "split_graph_launch", "split_graph_stats", "split_graph_destroy",
@@ -113,6 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.split_instance_set_coords.argtypes = [P, i32, P]
     lib.split_instance_set_dist.argtypes = [P, i32, P]
     lib.split_eval.argtypes = [P, P, i32, P, i64, i64, i32, P, P, P]
+    lib.split_eval_noalloc.argtypes = [P, P, i32, P, i64, i64, i32, P, P, P]
     lib.split_stats_get.argtypes = [P, ctypes.POINTER(SplitStatsC)]
     lib.split_eval_batch.argtypes = [P, P, P, i32, P, i64, i64, i32, P, i64, P, P, P]
     lib.split_batch_stats_get.argtypes = [P, P, P]
@@ -293,6 +295,29 @@ class SplitContext:
                                   ctypes.byref(out) if sync else None, sh)
         self._check(st)
         return cost, (self._stats(out) if sync else None)
+
+    def eval_noalloc(self, tour, demand, Q: int, cost, S: int | None = None, sync: bool = True,
+                     stream=None):
+        """split_eval_noalloc: split_eval with every per-call device buffer taken from the GPU's
+        fixed scratch (no allocation on the device). `cost` is the caller's contiguous CUDA
+        int32 tensor of >= S elements. Returns the SplitStats when sync, else None."""
+        import torch
+        np = _np()
+        t = np.ascontiguousarray(tour, dtype=np.int32)
+        ld, S = _demand_shape(demand, S, t, self.N)
+        if not (cost.is_cuda and cost.dtype == torch.int32 and cost.is_contiguous() and
+                cost.numel() >= S):
+            raise ValueError("cost must be a contiguous CUDA int32 tensor with >= S elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(demand.device)
+        out = SplitStatsC()
+        st = self._lib.split_eval_noalloc(self._h, t.ctypes.data_as(ctypes.c_void_p), len(t),
+                                          ctypes.c_void_p(demand.data_ptr()), S, ld, int(Q),
+                                          ctypes.c_void_p(cost.data_ptr()),
+                                          ctypes.byref(out) if sync else None,
+                                          ctypes.c_void_p(stream.cuda_stream))
+        self._check(st)
+        return self._stats(out) if sync else None
 
     def eval_batch(self, tours, demand, Q: int, S: int | None = None, cost=None,
                    sync: bool = True, stream=None):

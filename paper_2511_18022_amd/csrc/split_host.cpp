@@ -139,6 +139,9 @@ struct split_ctx {
     int64_t launches = 0;
     std::vector<float> ms_samples;  // per timed launch since the last reset
     const char *tname = "";
+
+    // device address of this GPU's fixed scratch (split_eval_noalloc), looked up at creation
+    unsigned char *scratch = nullptr;
 };
 
 struct split_graph {
@@ -654,6 +657,12 @@ split_status split_ctx_create(int hip_device, split_ctx **out)
         return SPLIT_E_NOMEM;
     }
     ctx->cus = prop.multiProcessorCount;
+    void *scr = nullptr;
+    if (scratch_address(hip_device, &scr) != hipSuccess) {
+        split_ctx_destroy(ctx);
+        return SPLIT_E_HIP;
+    }
+    ctx->scratch = static_cast<unsigned char *>(scr);
     for (int k = 0; k < kStages; ++k) {
         if (hipEventCreateWithFlags(&ctx->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
             split_ctx_destroy(ctx);
@@ -755,6 +764,89 @@ split_status split_eval(split_ctx *ctx, const int32_t *tour, int32_t n, const in
                                  (hipStream_t)hip_stream);
     if (st != SPLIT_OK) return st;
     if (stats) return split_stats_get(ctx, stats);
+    return SPLIT_OK;
+}
+
+// The largest call (a tour of SPLIT_MAX_N positions, 1024 moment blocks) fits the scratch.
+static_assert(((32 + 4 * (size_t)SPLIT_MAX_N + 255) & ~(size_t)255) +
+                  ((8 * ((size_t)SPLIT_MAX_N + 1 + kRowPad) + 255) & ~(size_t)255) +
+                  2 * ((4 * ((size_t)SPLIT_MAX_N + 1 + kRowPad) + 255) & ~(size_t)255) +
+                  2 * 256 + 24 * 1024 <= kScratchBytes,
+              "split_eval_noalloc: the scratch does not hold a maximal tour");
+
+split_status split_eval_noalloc(split_ctx *ctx, const int32_t *tour, int32_t n,
+                                const int16_t *demand, int64_t S, int64_t ld, int32_t Q,
+                                int32_t *cost, split_stats *stats, void *hip_stream)
+{
+    if (!ctx) return SPLIT_E_INVAL;
+    const char *who = "split_eval_noalloc";
+    if (ctx->inst.kind < 0) return fail(ctx, SPLIT_E_INVAL, "%s: no instance set", who);
+    if (!demand || !cost) return fail(ctx, SPLIT_E_INVAL, "%s: NULL pointer", who);
+    split_status st = check_shape(ctx, who, S, ld, Q, S);
+    if (st != SPLIT_OK) return st;
+    const int64_t tour_ptr[2] = {0, n};
+    BatchInfo bi;
+    st = check_tours(ctx, who, ctx->inst, ctx->seen, tour, tour_ptr, 1, S, &bi);
+    if (st != SPLIT_OK) return st;
+    split_tuning tu = ctx->tuning;
+    if (tu.form == SPLIT_FORM_MASK)
+        return fail(ctx, SPLIT_E_INVAL, "%s: the two-kernel form needs a mask matrix in device "
+                    "memory and is not available without allocation", who);
+
+    // Carve the call's device buffers from the scratch, each 256-byte aligned.
+    const StageLayout L = stage_layout(1, n);
+    const int64_t pos = (int64_t)n + 1 + kRowPad;
+    const int32_t nblk = moment_blocks(S);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_stage = 0;
+    const size_t o_rowoff = o_stage + up(L.bytes);
+    const size_t o_rowoff32 = o_rowoff + up(sizeof(int64_t) * (size_t)pos);
+    const size_t o_w = o_rowoff32 + up(sizeof(uint32_t) * (size_t)pos);
+    const size_t o_stats = o_w + up(sizeof(int32_t) * (size_t)pos);
+    const size_t o_ctl = o_stats + up(sizeof(DevStats));
+    const size_t o_part = o_ctl + up(sizeof(BatchCtl));
+    const size_t need = o_part + up(sizeof(unsigned long long) * 3 * (size_t)nblk);
+    if (need > kScratchBytes)
+        return fail(ctx, SPLIT_E_INVAL, "%s: a tour of %d positions needs %zu bytes of device "
+                    "scratch, above the fixed %zu", who, n, need, kScratchBytes);
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, SPLIT_E_HIP, "hipSetDevice failed");
+    EvalBuffers b;  // views of the scratch; nothing here is owned or freed
+    b.d_stage = reinterpret_cast<char *>(ctx->scratch + o_stage);
+    b.cap_stage = (int64_t)L.bytes;
+    b.d_rowoff = reinterpret_cast<int64_t *>(ctx->scratch + o_rowoff);
+    b.d_rowoff32 = reinterpret_cast<uint32_t *>(ctx->scratch + o_rowoff32);
+    b.d_w = reinterpret_cast<int32_t *>(ctx->scratch + o_w);
+    b.cap_pos = pos;
+    b.d_stats = reinterpret_cast<DevStats *>(ctx->scratch + o_stats);
+    b.cap_T = 1;
+    b.d_ctl = reinterpret_cast<BatchCtl *>(ctx->scratch + o_ctl);
+    b.d_partials = reinterpret_cast<unsigned long long *>(ctx->scratch + o_part);
+    b.cap_partials = nblk;
+
+    // The staged header of a batch of one: T, tptr, order, then the tour itself, copied from
+    // pageable host memory (the runtime stages it before the call returns).
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    const int64_t head[3] = {1, 0, n};
+    const int32_t order0 = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(b.d_stage, head, sizeof head, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b.d_stage + L.off_order, &order0, sizeof order0,
+                                hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b.d_stage + L.off_tours, tour, sizeof(int32_t) * (size_t)n,
+                                hipMemcpyHostToDevice, stream));
+    const Plan p = make_plan(ctx, tu, S, ld, Q, 1, bi.maxn, bi.max_id);
+    // the prep kernel zeroes the result block and the counters of every call
+    st = enqueue_kernels(ctx, ctx->inst, b, L, p, demand, S, ld, Q, cost, S, stream, false);
+    if (st != SPLIT_OK) return st;
+    if (!stats) return SPLIT_OK;
+    DevStats d;
+    HIP_TRY(ctx, hipMemcpyAsync(&d, b.d_stats, sizeof d, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    fill_stats(d, S, stats);
+    if (d.err_demand)
+        return fail(ctx, SPLIT_E_DEMAND, "%s: a scenario has a demand q < 0 or q > Q on the tour",
+                    who);
     return SPLIT_OK;
 }
 

@@ -134,4 +134,11 @@ int32_t moment_blocks(int64_t S);
 const char *lane_kernel_name();
 const char *wave_kernel_name();
 
+// Device scratch of the allocation-free evaluation: kScratchBytes per GPU, 256-byte aligned.
+// scratch_address returns its device address on `device`, which must be the current device
+// (looked up once per device, then cached).
+constexpr size_t kScratchBytes = 192 * 1024;
+constexpr int kMaxScratchDevices = 64;
+hipError_t scratch_address(int device, void **out);
+
 }  // namespace splitgpu

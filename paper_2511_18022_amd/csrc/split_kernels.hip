@@ -22,6 +22,8 @@
 //  split_moments_*        exact 128-bit sum and sum of squares of the costs.
 #include "split_internal.h"
 
+#include <mutex>
+
 namespace splitgpu {
 
 // ------------------------------------------------------------------------- distances
@@ -923,6 +925,35 @@ __global__ __launch_bounds__(256) void split_moments_final(MomentArgs a)
         a.stats[t].sq_lo = lo;
         a.stats[t].sq_hi = hi;
     }
+}
+
+// ------------------------------------------------------------------------- scratch
+
+// Fixed device scratch of the allocation-free evaluation (split_eval_noalloc): every per-call
+// device buffer of a one-tour evaluation (staged tour, per-position arrays, result block,
+// counters, moment partials) is carved from it. Each GPU holds its own copy for the life of the
+// process; its device address is looked up once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static void *addr[kMaxScratchDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------------- launchers
