@@ -31,12 +31,25 @@ METRIC_SCREEN = "screened tours/s at regret (1000 customers, S=65536, top 1% re-
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 METRIC_SEARCH = "expected cost after a timed local search (1000 customers, 10^4 in-sample scenarios)"
 HBM_PEAK_GBS = 8000.0
+SETTLE_S = 0.5  # untimed sustained work before the warm-up steps (clock ramp)
 # INT32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 KERNEL_SRC = os.path.join(ROOT, "paper_2511_18022_amd", "csrc", "split_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 COPULA_DESC = ("int16 [N][S]; Gaussian copula, AR(1) 0.6 along customer id, lognormal mean 20 "
                "CV 0.5")
+
+
+def metric_name(workload: str, batch: bool, T: int, S: int, sum_n: int) -> str:
+    """The headline metric's name for the recipes it is quoted on; otherwise one that names the
+    workload that was run."""
+    if not batch and workload == "copula-n1000" and S == 1 << 20:
+        return METRIC
+    if batch and workload == "batch-256" and T == 256 and S == 65536:
+        return METRIC_BATCH
+    if batch:
+        return f"Split scenario-evals/s, {workload} ({T} tours, {sum_n} positions, S={S})"
+    return f"Split scenario-evals/s, {workload} (n={sum_n}, S={S})"
 
 
 def log(msg):
@@ -212,11 +225,19 @@ def calibrate_copy(nbytes: int = 2 << 30, reps: int = 3):
                       "ms_per_copy": el * 1e3, "GBps_read_plus_write": 2 * nbytes / el / 1e9}))
 
 
-def timed_steps(ctx, step, wait, steps: int, warmup: int):
+def timed_steps(ctx, step, wait, steps: int, warmup: int, settle_s: float = SETTLE_S):
     """Warm-up steps, then `steps` timed steps between device synchronizations, with the
     dominant kernel of eager evaluations timed by HIP events on their stream. Returns
     (ms per step, dominant-kernel average ms, kernel name, timed launches, median ms)."""
     import torch
+    # the GPU's clocks ramp over the first few hundred milliseconds of sustained work: untimed
+    # evaluations for at least settle_s seconds come before the warm-up steps
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < settle_s:
+        for _ in range(10):
+            step()
+        wait()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         step()
     wait()
@@ -287,6 +308,12 @@ def run_screen(args, threads):
     loss = net.train(tr, lab, batch=args.batch, steps=steps, lr=args.lr, seed=3)
     train_s = time.perf_counter() - t0
     log(f"trained {steps} steps (batch {args.batch}) in {train_s:.2f}s, mean loss {loss:.4f}")
+    # MFMA work of one training step, per tour of n positions (8 input features, 128 channels,
+    # 5 taps): forward 2n*128*(5*8 + 3*5*128), data gradients of layers 2-4 2n*128*(3*5*128),
+    # weight gradients 2n*128*(5*8 + 3*5*128)
+    n_tr = int(w.train.shape[1])
+    train_flops_step = 2.0 * n_tr * 128 * (2 * (5 * 8 + 3 * 5 * 128) + 3 * 5 * 128) * args.batch
+    train_tflops = train_flops_step * steps / train_s / 1e12
     # screening, timed: predict every candidate, keep the top 1%, evaluate those exactly
     res = net.screen(ca[:min(C, 4096)], max(1, min(C, 4096) // 100), dem, w.Q)  # warm-up
     torch.cuda.synchronize()
@@ -339,7 +366,16 @@ def run_screen(args, threads):
         "dtype": "bf16 (surrogate), int32 (exact Split)",
         "data": "synthetic",
         "regret": regret,
+        "regret_target": 0.005,
         "exact_only": {"tours_per_s": C / exact_s, "seconds": exact_s, "best_mean": means[best]},
+        "train_roofline": {"bound": "mfma", "achieved": train_tflops,
+                           "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS,
+                           "flops_per_step": train_flops_step, "steps": steps,
+                           "ms_per_step": train_s * 1e3 / steps,
+                           "what": "whole training steps by wall time (features, conv forward, "
+                                   "data and weight gradients, head, Adam); per-kernel times "
+                                   "in the committed rocprofv3 summary"},
         "speedup_vs_exact_only": exact_s / screen_s,
         "config": {"workload": "screen", "N": n, "S": w.S, "Q": w.Q, "candidates": C,
                    "keep": w.keep, "train_tours": ntrain, "train_steps": steps,
@@ -504,7 +540,8 @@ def run_scaling(args, threads):
         def step():
             ctx.eval(w.tour, sl, w.Q, cost=cost, sync=False)
         ms, kern_ms, kname, launches, kern_med = timed_steps(ctx, step, ctx.batch_stats,
-                                                             args.steps, args.warmup)
+                                                             args.steps, args.warmup,
+                                                             args.settle)
         stats, _ = ctx.batch_stats()
         M = window_work(sl, [w.tour], w.Q)
         ops = M / 2 + 4 * w.n * S
@@ -563,15 +600,69 @@ def run_scaling(args, threads):
     ctx.close()
 
 
+def run_crossover(args, threads):
+    """Whole evaluations (prep, Split DP, moments, statistics copy) in both kernel forms for
+    short tours over few scenarios: the first n positions of the n = 1000 copula tour, over its
+    first S scenarios. The crossover sets the automatic form choice."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2511_18022_amd as sg
+    w = gen.make_workload("copula-n1000", S=4096, threads=threads)
+    ctx = sg.SplitContext(0)
+    ctx.set_coords(w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    cost = torch.empty(w.S, dtype=torch.int32, device="cuda")
+
+    def timed(tour, S, form):
+        ctx.set_form(form)
+        sl = dem[:, :S]
+        for _ in range(10):
+            ctx.eval(tour, sl, w.Q, cost=cost, sync=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            ctx.eval(tour, sl, w.Q, cost=cost, sync=False)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps * 1e3, cost[:S].cpu().numpy()
+
+    for _ in range(200):  # clock ramp
+        ctx.eval(w.tour, dem, w.Q, cost=cost, sync=False)
+    torch.cuda.synchronize()
+    points = []
+    for S in (256, 1024, 4096):
+        for n in (8, 16, 24, 32, 48, 64, 96, 128, 256):
+            tour = np.ascontiguousarray(w.tour[:n])
+            us_lane, c_lane = timed(tour, S, "lane")
+            us_wave, c_wave = timed(tour, S, "wave")
+            assert np.array_equal(c_lane, c_wave)
+            points.append({"S": S, "n": n, "lane_us": us_lane, "wave_us": us_wave,
+                           "faster": "wave" if us_wave < us_lane else "lane"})
+            log(f"S={S} n={n}: lane {us_lane:.1f} us, wave {us_wave:.1f} us")
+    print(json.dumps({"metric": "whole-evaluation time per kernel form (form crossover)",
+                      "unit": "us", "steps": args.steps, "data": "synthetic",
+                      "config": {"workload": "crossover", "instance": "copula-n1000"},
+                      "points": points}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     # the GPU's clocks need a few tens of milliseconds of work to settle
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--settle", type=float, default=SETTLE_S,
+                    help="seconds of untimed evaluations before the warm-up steps (clock ramp)")
     ap.add_argument("--workload", default="copula-n1000")
     ap.add_argument("--form", default="auto", choices=["auto", "lane", "wave", "mask"])
     ap.add_argument("--tours", type=int, default=None, help="batch workloads: number of tours")
+    ap.add_argument("--scenarios", type=int, default=None,
+                    help="evaluate the workload's first S scenarios instead of all (a profiling "
+                         "and form-comparison run; the headline uses the full recipe)")
     ap.add_argument("--launch", default="graph", choices=["eager", "graph"],
                     help="time eager calls or replays of a captured graph of the same "
                          "evaluation (the kernel's HIP-event duration always comes from eager "
@@ -585,8 +676,8 @@ def main():
                     help="skip counting the window work that sizes the ALU roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 2 GiB (HBM counter scale)")
-    ap.add_argument("--candidates", type=int, default=100_000,
-                    help="screen workload: candidate tours (the full recipe has 1,000,000)")
+    ap.add_argument("--candidates", type=int, default=1_000_000,
+                    help="screen workload: candidate tours")
     ap.add_argument("--train", type=int, default=100_000, help="screen workload: training tours")
     ap.add_argument("--epochs", type=int, default=2, help="screen workload: training epochs")
     ap.add_argument("--batch", type=int, default=128, help="screen workload: training batch")
@@ -627,16 +718,20 @@ def main():
     if args.workload == "scaling":
         run_scaling(args, threads)
         return
+    if args.workload == "crossover":
+        run_crossover(args, threads)
+        return
     batch = args.workload in gen.BATCH_RECIPES
     t0 = time.perf_counter()
     if batch:
-        w = gen.make_batch_workload(args.workload, T=args.tours, threads=threads)
+        w = gen.make_batch_workload(args.workload, T=args.tours, S=args.scenarios,
+                                    threads=threads)
         tours = w.tours
         lens = [len(t) for t in tours]
         log(f"generated {args.workload}: T={len(tours)} n in [{min(lens)}, {max(lens)}] "
             f"(sum {sum(lens)}) S={w.S} Q={w.Q} in {time.perf_counter() - t0:.1f}s")
     else:
-        w = gen.make_workload(args.workload, threads=threads)
+        w = gen.make_workload(args.workload, S=args.scenarios, threads=threads)
         tours = [w.tour]
         log(f"generated {args.workload}: n={w.n} S={w.S} Q={w.Q} in "
             f"{time.perf_counter() - t0:.1f}s")
@@ -677,14 +772,14 @@ def main():
 
     # eager evaluations: the dominant kernel's duration for the roofline
     ms_eager, kern_avg_ms, kname, launches, kern_med_ms = timed_steps(
-        ctx, step, ctx.batch_stats, args.steps, args.warmup)
+        ctx, step, ctx.batch_stats, args.steps, args.warmup, args.settle)
     stats, status = ctx.batch_stats()
     ms_step = ms_eager
     if launch == "graph":
         g = ctx.graph(T, sum(len(t) for t in tours), dem, w.Q,
                       cost=cost if batch else cost.view(1, -1))
         ms_step, _, _, _, _ = timed_steps(ctx, lambda: g.launch(tours), g.stats, args.steps,
-                                          args.warmup)
+                                          args.warmup, args.settle)
         gstats, gstatus = g.stats()
         assert [s.sum for s in gstats] == [s.sum for s in stats] and gstatus == status
         g.close()
@@ -750,7 +845,7 @@ def main():
                      "kernel_median_ms": kern_med_ms,
                      "algorithmic_bytes_per_launch": algo_bytes})
     out = {
-        "metric": METRIC_BATCH if batch else METRIC,
+        "metric": metric_name(w.name, batch, T, w.S, sum_n),
         "value": evals / (ms_step * 1e-3),
         "unit": "scenario-evals/s",
         "n_gpus": 1,

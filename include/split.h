@@ -48,7 +48,9 @@ typedef enum {
 
 /* Kernel form used by split_eval (all compute identical results). */
 typedef enum {
-    SPLIT_FORM_AUTO = 0, /* scenario-per-lane for large S, wavefront-per-scenario for small S */
+    SPLIT_FORM_AUTO = 0, /* wavefront-per-scenario for short tours over few scenarios (n <= 32
+                            at S <= 256, n <= 24 at S <= 1024, n <= 16 at S <= 4096),
+                            scenario-per-lane otherwise */
     SPLIT_FORM_LANE = 1, /* one scenario per lane; sliding-window minimum in LDS (Q <= 16383;
                             a larger Q runs in the wave form) */
     SPLIT_FORM_WAVE = 2, /* one scenario per wavefront; lanes over predecessors p */
@@ -187,7 +189,8 @@ split_status split_set_form(split_ctx *ctx, int form);
 /*
  * Launch choices of the evaluations (none changes a result: every choice computes exactly
  * Section 3's Eqs. (1)-(3)).
- *  form         split_form; SPLIT_FORM_AUTO takes the wave form up to S = 4096, else the lane form.
+ *  form         split_form; SPLIT_FORM_AUTO takes the wave form for short tours over few
+ *               scenarios (see split_form), else the lane form.
  *  lane_per_cu  lane form: 0 = one workgroup per work item (a tour and 64 of its scenarios);
  *               1..8 = that many persistent workgroups per compute unit, taking work items
  *               from a queue.

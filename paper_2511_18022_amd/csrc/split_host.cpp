@@ -20,7 +20,18 @@ using namespace splitgpu;
 namespace {
 
 constexpr int kStages = 8;              // pinned host slots for tour uploads
-constexpr int64_t kWaveAutoMaxS = 4096;  // SPLIT_FORM_AUTO uses the wave form up to this S
+// SPLIT_FORM_AUTO takes the wave form for short tours over few scenarios, where the lane
+// kernel's per-item prologue outweighs its per-state advantage. Measured crossover of whole
+// evaluations (tours of 8..256 positions): the wave form is ahead up to n = 32 at S = 256, up to
+// n = 24 at S = 1024 and up to n = 16 at S = 4096; the lane form everywhere else (at n = 1000
+// from S = 1024 on, at 2.6x and more).
+bool auto_wave(int64_t S, int32_t maxn)
+{
+    if (S <= 256) return maxn <= 32;
+    if (S <= 1024) return maxn <= 24;
+    if (S <= 4096) return maxn <= 16;
+    return false;
+}
 // The lane kernel compares load differences in 16 bits, exact while 8 * max(q) + Q < 2^15;
 // evaluations with a larger capacity run in the wave form, which is exact for any Q.
 constexpr int32_t kLaneMaxQ = 16383;
@@ -440,7 +451,7 @@ Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t 
 {
     Plan p;
     p.form = tu.form;
-    if (p.form == SPLIT_FORM_AUTO) p.form = S <= kWaveAutoMaxS ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
+    if (p.form == SPLIT_FORM_AUTO) p.form = auto_wave(S, maxn) ? SPLIT_FORM_WAVE : SPLIT_FORM_LANE;
     // past the lane kernel's 16-bit bound every scenario would be handed to the wave kernel
     if (p.form == SPLIT_FORM_LANE && Q > kLaneMaxQ) p.form = SPLIT_FORM_WAVE;
     // the lane kernel addresses demands with 32-bit buffer offsets

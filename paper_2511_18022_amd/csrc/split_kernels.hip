@@ -222,15 +222,18 @@ __device__ __forceinline__ int exact_start(LaneLds &L, int lane, int S, uint32_t
 // position does not exist). Writes the ring rows of the block and returns the packed
 // thresholds TT[k] = (P_{16c+2k} - Q, P_{16c+2k+1} - Q) mod 2^16.
 template <int R>
-__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint32_t (&q)[kLB],
+__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint16_t (&q)[kLB],
                                             uint32_t QQ, uint32_t &Plast, uint32_t &qor,
                                             uint32_t (&TT)[kLB / 2])
 {
     uint32_t prev = Plast;
 #pragma unroll
     for (int k = 0; k < kLB / 2; ++k) {
-        const uint32_t q0 = q[2 * k], q1 = q[2 * k + 1];
-        const uint32_t E = ((q0 + q1) << 16) + q0;  // (q0, q0 + q1)
+        // (q0, q1) packed by one byte permutation, then (q0, q0 + q1): the low half shifted
+        // into the high half adds q0 there and leaves the low half alone
+        const u16x2 qv = {q[2 * k], q[2 * k + 1]};
+        const uint32_t Qp = __builtin_bit_cast(uint32_t, qv);
+        const uint32_t E = Qp + (Qp << 16);
         const u16x2 ev = __builtin_bit_cast(u16x2, E);
         const u16x2 pv = __builtin_bit_cast(u16x2, prev);
         const u16x2 bc = {pv.y, pv.y};
@@ -238,7 +241,7 @@ __device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint32_t
         prev = PP;
         TT[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, PP) -
                                                  __builtin_bit_cast(u16x2, QQ));
-        qor |= q0 | q1;
+        qor |= Qp;  // both halves: the bound below takes the larger
         constexpr int row0 = 8 * R;
         L.pp[(row0 + k) & (kRingPairs - 1)][lane] = PP;
         if (((row0 + k) & (kRingPairs - 1)) < kMirror)
@@ -271,8 +274,12 @@ __device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int fi
         const uint32_t a23 = sign_bytes(pk_sub16(d3, T), pk_sub16(d2, T));
         const int base = Sp & ~0x80;
         int Sn = base + (int)((__builtin_popcount(a23) + __builtin_popcount(a01)) << 4);
-        const bool redo = (int32_t)a23 < 0 || s_of(base) + 7 > first + kLB - 1;
-        if (redo) Sn = exact_start(L, lane, Sp, T);
+        // A short count (the eighth position expired too) is exact up to its end: every counted
+        // position expired, so the walk continues from there. A read past the written prefix
+        // loads (first + 15) may have counted stale positions: the walk starts over from Sp.
+        const bool past = s_of(base) + 7 > first + kLB - 1;
+        const bool redo = (int32_t)a23 < 0 || past;
+        if (redo) Sn = exact_start(L, lane, past ? Sp : Sn, T);
         sOut[t] = Sn;
         Sp = Sn;
     }
@@ -281,13 +288,6 @@ __device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int fi
 // Materializes v at this point of the instruction stream (keeps the compiler from sinking a
 // computation towards a later use).
 __device__ __forceinline__ void pin(int &v) { asm volatile("" : "+v"(v)); }
-__device__ __forceinline__ void pin_uniform16(int (&v)[16])
-{
-    asm volatile(""
-                 : "+s"(v[0]), "+s"(v[1]), "+s"(v[2]), "+s"(v[3]), "+s"(v[4]), "+s"(v[5]),
-                   "+s"(v[6]), "+s"(v[7]), "+s"(v[8]), "+s"(v[9]), "+s"(v[10]), "+s"(v[11]),
-                   "+s"(v[12]), "+s"(v[13]), "+s"(v[14]), "+s"(v[15]));
-}
 
 // The 12 positions a pair reads (6 packed dwords) and the even position they start at.
 struct PairData {
@@ -430,11 +430,27 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
 // past n with a valid row, so blocks past n load unguarded (their values are not used).
 __device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
                                                 cu32 *__restrict__ rowoff,
-                                                uint32_t lane_off, int blk, uint32_t (&q)[kLB])
+                                                uint32_t lane_off, int blk, uint16_t (&q)[kLB])
 {
 #pragma unroll
     for (int t = 0; t < kLB; ++t)
         q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t], 0);
+}
+
+// The 16 weights of block blk by vector loads (every lane the same 16 bytes, four times): a
+// scalar load here would need a wait that also drains every outstanding LDS operation.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void lane_load_w(__amdgpu_buffer_rsrc_t wrsrc, int blk, int (&wv)[kLB])
+{
+#pragma unroll
+    for (int j = 0; j < kLB / 4; ++j) {
+        const i32x4 v = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                       wrsrc, 0, (blk * kLB + 4 * j) * 4, 0));
+        wv[4 * j] = v.x;
+        wv[4 * j + 1] = v.y;
+        wv[4 * j + 2] = v.z;
+        wv[4 * j + 3] = v.w;
+    }
 }
 
 struct LaneState {
@@ -449,13 +465,17 @@ struct LaneState {
 // block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 3.
 template <int R>
 __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, uint32_t QQ,
-                                          __amdgpu_buffer_rsrc_t dem,
+                                          __amdgpu_buffer_rsrc_t dem, __amdgpu_buffer_rsrc_t wrsrc,
                                           cu32 *__restrict__ rowoff, uint32_t lane_off,
-                                          ci32 *__restrict__ w, const uint32_t (&qUse)[kLB],
-                                          uint32_t (&qLoad)[kLB], const int (&sCur)[kLB],
-                                          int (&sNext)[kLB], LaneState &st)
+                                          ci32 *__restrict__ w, const uint16_t (&qUse)[kLB],
+                                          uint16_t (&qLoad)[kLB], const int (&sCur)[kLB],
+                                          int (&sNext)[kLB], const int (&wUse)[kLB],
+                                          int (&wLoad)[kLB], LaneState &st)
 {
-    lane_load_block(dem, rowoff, lane_off, c + 3, qLoad);  // unconditional: exact wait counts
+    // weights of block c + 1 (used by the next step), demands of block c + 3; unconditional,
+    // so that every path has the same vector-memory wait counts
+    lane_load_w(wrsrc, c + 1, wLoad);
+    lane_load_block(dem, rowoff, lane_off, c + 3, qLoad);
     const int nb = n >> 4;
     if (c > nb) return;
     const int p0 = c * kLB;
@@ -473,12 +493,10 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
         // first state of pair u-1, then second state of pair u (whose read was issued at the
         // end of iteration u-1) and the read of pair u+1. The scheduling barriers keep the
         // independent work between each read and its first use.
-        // the block's weights, loaded up front: a scalar load inside the pipeline would make
-        // its wait drain every outstanding LDS read as well
+        // the block's weights, in vector registers since the previous step
         int wv[kLB];
 #pragma unroll
-        for (int t = 0; t < kLB; ++t) wv[t] = w[p0 + t];
-        pin_uniform16(wv);
+        for (int t = 0; t < kLB; ++t) wv[t] = wUse[t];
         uint32_t TT[kLB / 2];
         lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
         uint32_t qd[kLB];
@@ -575,13 +593,17 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
     st.ovf = false;
 
     const int nb = n >> 4;
-    uint32_t qA[kLB], qB[kLB], qC[kLB], qD[kLB];
+    uint16_t qA[kLB], qB[kLB], qC[kLB], qD[kLB];
     int sA[kLB], sB[kLB];
+    int wA[kLB], wB[kLB];  // weights of the block a step evaluates, loaded one step ahead
+    const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.tour.w + ab), (short)0, (int)(sizeof(int32_t) * (n + 1 + kRowPad)), 0x00020000);
 #pragma unroll
     for (int k = 0; k < kLB; ++k) {
         sA[k] = S_of(0, lane);
         sB[k] = S_of(0, lane);
     }
+    lane_load_w(wrsrc, 0, wA);
     lane_load_block(rsrc, rowoff, lane_off, 0, qA);
     lane_load_block(rsrc, rowoff, lane_off, 1, qB);
     lane_load_block(rsrc, rowoff, lane_off, 2, qC);
@@ -594,15 +616,15 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
     // block b's demands live in q[A, B, C, D][b & 3] and the starts rotate between sA and sB;
     // four steps per iteration keep these roles and the ring rows of every step constant
     for (int c = 0; c <= nb; c += 4) {
-        lane_step<0>(L, lane, c, n, QQ, rsrc, rowoff, lane_off, w, qB, qD, sA, sB, st);
-        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, rowoff, lane_off, w, qC, qA, sB, sA, st);
-        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, rowoff, lane_off, w, qD, qB, sA, sB, st);
-        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, rowoff, lane_off, w, qA, qC, sB, sA, st);
+        lane_step<0>(L, lane, c, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qB, qD, sA, sB, wA, wB, st);
+        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qC, qA, sB, sA, wB, wA, st);
+        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qD, qB, sA, sB, wA, wB, st);
+        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qA, qC, sB, sA, wB, wA, st);
     }
 
     // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
     // int16 demand) also lands here, and the general kernel reports it
-    st.ovf |= 8u * st.qor + (uint32_t)Q > 32767u;
+    st.ovf |= 8u * ((st.qor | (st.qor >> 16)) & 0xFFFFu) + (uint32_t)Q > 32767u;
     int32_t *cost = a.cost + (long long)t * a.ldc;
     if (active) {
         if (st.ovf) {

@@ -17,6 +17,8 @@ cancels and flips are rare. So:
 """
 import os
 
+import time
+
 import numpy as np
 import pytest
 
@@ -407,9 +409,42 @@ def test_screening_gain_over_the_method_without_the_network(sg):
         # the shortlist's exact means are the exact means of those candidates
         assert np.array_equal(res["short_mean"], truth[res["short_idx"]])
         net.close()
+    # the method without the network at the same exact-evaluation budget: K candidates drawn at
+    # random (seeded), the best of them by exact mean
+    rng = np.random.default_rng(77)
+    rand_regret = [float((truth[rng.choice(len(truth), size=K, replace=False)].min() - best) / best)
+                   for _ in range(20)]
     print(f"[nn] screening gain: regret and rank correlation {out}, {K} of {len(w.cands)} "
-          "evaluated exactly", flush=True)
+          f"evaluated exactly; random {K}-shortlists: median regret "
+          f"{float(np.median(rand_regret)):.4f}, best {min(rand_regret):.4f}", flush=True)
     assert out["trained"][0] <= 0.005
     assert out["trained"][1] >= 0.9
     assert out["trained"][1] >= out["untrained"][1] + 0.3
+    # a random 5% shortlist holds the best candidate with probability 0.05: compare with the
+    # typical (median) random shortlist, not the luckiest of the 20 draws
+    assert out["trained"][0] < float(np.median(rand_regret))
+    # and against exact evaluation of every candidate: screening (prediction of all, exact
+    # evaluation of the shortlist) takes less time for the same best tour
+    net = sg.SplitNN(ctx, seed=1, length_scale=1000.0)
+    net.set_scenarios(dem, w.Q)
+    net.set_norm(float(labels.mean()), float(labels.std()))
+    net.train(torch.from_numpy(w.train).cuda(), torch.from_numpy(labels.astype(np.float32)).cuda(),
+              batch=128, steps=6 * (len(w.train) // 128), lr=1e-3, seed=3)
+    net.screen(ca, K, dem, w.Q)  # warm-up
+    t_screen, t_exact = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = net.screen(ca, K, dem, w.Q)
+        torch.cuda.synchronize()
+        t_screen.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        exact(w.cands)
+        torch.cuda.synchronize()
+        t_exact.append(time.perf_counter() - t0)
+    print(f"[nn] screening {len(w.cands) / min(t_screen):.0f} tours/s against exact-only "
+          f"{len(w.cands) / min(t_exact):.0f} tours/s", flush=True)
+    assert (res["best_mean"] - best) / best <= 0.005
+    assert min(t_screen) < min(t_exact)
+    net.close()
     ctx.close()

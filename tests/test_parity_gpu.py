@@ -347,3 +347,21 @@ def test_kernel_timing_totals_and_samples(ctx):
     assert len(ctx.timing_samples()) == 5  # untimed calls add nothing
     ctx.timing_reset()
     assert len(ctx.timing_samples()) == 0 and ctx.timing_get()[:2] == (0.0, 0)
+
+
+@pytest.mark.parametrize("workload,S,kernel", [("uniform-n20", 1000, "split_wave_kernel"),
+                                               ("uniform-n20", 256, "split_wave_kernel"),
+                                               ("uniform-n20", 4096, "split_lane_kernel"),
+                                               ("poisson-n200", 1000, "split_lane_kernel"),
+                                               ("uniform-n20", 8192, "split_lane_kernel")])
+def test_automatic_form_choice(ctx, workload, S, kernel):
+    # AUTO: wave form for short tours over few scenarios (n <= 24 at S <= 1024 here, the
+    # measured crossover), lane form otherwise; the result is the oracle's either way
+    w = gen.make_workload(workload, S=S)
+    d = oracle.dist_matrix(w.xy)
+    ctx.timing(True)
+    ctx.timing_reset()
+    check_against_oracle(ctx, w.tour, w.demand, w.Q, d, form="auto", xy=w.xy)
+    name = ctx.timing_get()[2]
+    ctx.timing(False)
+    assert name == kernel
