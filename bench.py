@@ -671,6 +671,9 @@ def main():
                     help="batch workloads: keep the default launch choices")
     ap.add_argument("--tuning", default=None, metavar="PER_CU,ORDER",
                     help="lane form with these launch choices instead of autotuning")
+    ap.add_argument("--lane-block", type=int, default=0, choices=[0, 8, 16],
+                    help="lane form: states per block of the scenario-per-lane kernel (0: the "
+                         "library default, 16; 8 suits windows shorter than about 24)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alu-count", action="store_true",
                     help="skip counting the window work that sizes the ALU roofline")
@@ -739,6 +742,7 @@ def main():
 
     ctx = sg.SplitContext(0)
     ctx.set_coords(w.xy)
+    ctx.set_tuning(sg.SplitTuning(lane_block=args.lane_block))
     ctx.set_form(args.form)
     t0 = time.perf_counter()
     dem = torch.from_numpy(w.demand).cuda()
@@ -752,13 +756,14 @@ def main():
         cost = torch.empty((T, w.S), dtype=torch.int32, device="cuda")
         if args.tuning:
             pc, order = (int(x) for x in args.tuning.split(","))
-            ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, pc, order, 0))
-            tuning = {"form": sg.FORM_LANE, "lane_per_cu": pc, "order": order, "wave_grid": 0}
+            ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, pc, order, 0, args.lane_block))
+            tuning = {"form": sg.FORM_LANE, "lane_per_cu": pc, "order": order, "wave_grid": 0,
+                      "lane_block": args.lane_block}
         elif not args.no_autotune:
             t0 = time.perf_counter()
             tu, tune_ms, _ = ctx.autotune(tours, dem, w.Q, reps=3)
             tuning = {"form": tu.form, "lane_per_cu": tu.lane_per_cu, "order": tu.order,
-                      "wave_grid": tu.wave_grid}
+                      "wave_grid": tu.wave_grid, "lane_block": tu.lane_block}
             log(f"autotune: {tu} {tune_ms:.4f} ms per evaluation "
                 f"({time.perf_counter() - t0:.1f}s)")
 
@@ -809,7 +814,8 @@ def main():
 
     config = {"workload": w.name, "S": w.S, "Q": w.Q, "seed": w.seed, "demand": COPULA_DESC,
               "coords": "integer uniform 1000x1000, rounded Euclidean int32 costs",
-              "kernel": kname, "form": args.form, "fallback_scenarios": n_fallback,
+              "kernel": kname, "form": args.form, "lane_block": ctx.tuning().lane_block or 16,
+              "fallback_scenarios": n_fallback,
               "launch": launch, "eager_ms_per_step": ms_eager,
               "h2d_GBps": dem.numel() * 2 / h2d_s / 1e9}
     if tuning is not None:

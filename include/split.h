@@ -196,13 +196,19 @@ split_status split_set_form(split_ctx *ctx, int form);
  *               from a queue.
  *  order        lane form: 0 = work items of longer tours first, 1 = tours in the given order.
  *  wave_grid    wave form: workgroups of the launch; 0 = min(T * S, 65536).
- * The default is {SPLIT_FORM_AUTO, 0, 0, 0}. split_set_form sets `form` alone.
+ *  lane_block   lane form: states per block of the scenario-per-lane kernel, 0 or 16 = 16,
+ *               or 8. A block's windows (Eq. (3)) are looked up in O(1) while they start
+ *               before the block; 16 suits windows of about 16..47 positions, 8 shorter ones
+ *               (about 8..23 positions; Q / mean demand estimates the window). Scenarios whose
+ *               windows outgrow three blocks are finished exactly by the wave kernel either way.
+ * The default is {SPLIT_FORM_AUTO, 0, 0, 0, 0}. split_set_form sets `form` alone.
  */
 typedef struct {
     int32_t form;
     int32_t lane_per_cu;
     int32_t order;
     int32_t wave_grid;
+    int32_t lane_block;
 } split_tuning;
 
 /* Set / read the context's launch choices. Errors: SPLIT_E_INVAL (a field out of range). */
@@ -213,8 +219,10 @@ split_status split_tuning_get(split_ctx *ctx, split_tuning *tuning);
  * Autotuner: times whole evaluations (tour upload, kernels, statistics; HIP events on
  * hip_stream, `reps` timed calls after one warm-up each) of this batch under the candidate
  * launch choices, installs the fastest in the context and returns it with its mean
- * milliseconds (either output may be NULL). Candidates: lane form with lane_per_cu in
- * {0, 8, 4, 2} and both orders; wave form with wave_grid in {0, 8 per CU} when a run on 256
+ * milliseconds (either output may be NULL). Candidates: lane form with lane_block 16 and 8
+ * (lane_per_cu 0, order 0; 8 only when, over the first 4096 scenarios, it leaves no more
+ * scenarios to the wave kernel than 16 does), then lane_per_cu in {0, 8, 4, 2} and both orders
+ * with the faster block length; wave form with wave_grid in {0, 8 per CU} when a run on 256
  * scenarios, scaled to S, comes within 1.5x of the best lane time. Arguments as in
  * split_eval_batch; `cost` is overwritten and ends holding the batch's costs under the chosen
  * tuning, and the context's latest evaluation (split_batch_stats_get) is that one.

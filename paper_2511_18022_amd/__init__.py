@@ -57,7 +57,8 @@ class SplitStatsC(ctypes.Structure):
 
 class SplitTuningC(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("lane_per_cu", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("wave_grid", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("wave_grid", ctypes.c_int32),
+                ("lane_block", ctypes.c_int32)]
 
 
 @dataclass
@@ -67,13 +68,16 @@ class SplitTuning:
     lane_per_cu: int = 0
     order: int = 0
     wave_grid: int = 0
+    lane_block: int = 0
 
     def to_c(self) -> SplitTuningC:
-        return SplitTuningC(self.form, self.lane_per_cu, self.order, self.wave_grid)
+        return SplitTuningC(self.form, self.lane_per_cu, self.order, self.wave_grid,
+                            self.lane_block)
 
     @staticmethod
     def from_c(c: SplitTuningC) -> "SplitTuning":
-        return SplitTuning(int(c.form), int(c.lane_per_cu), int(c.order), int(c.wave_grid))
+        return SplitTuning(int(c.form), int(c.lane_per_cu), int(c.order), int(c.wave_grid),
+                           int(c.lane_block))
 
 
 class SplitSearchResultC(ctypes.Structure):

@@ -96,7 +96,7 @@ struct BatchInfo {
 // What the kernels of one evaluation are launched with.
 struct Plan {
     int form = SPLIT_FORM_LANE;
-    int32_t lane_grid = 0, wave_grid = 0, maxn = 0;
+    int32_t lane_grid = 0, wave_grid = 0, maxn = 0, lane_block = 16;
     uint32_t lane_bytes = 0;
 };
 
@@ -122,7 +122,7 @@ struct split_ctx {
     int device = 0;
     int cus = 0;
     std::string err;
-    split_tuning tuning = {SPLIT_FORM_AUTO, 0, 0, 0};
+    split_tuning tuning = {SPLIT_FORM_AUTO, 0, 0, 0, 0};
 
     Instance inst;
     std::vector<unsigned char> seen;
@@ -462,6 +462,7 @@ Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t 
     const int64_t items = (S + 63) / 64 * T_grid;
     const int64_t lg = tu.lane_per_cu <= 0 ? items : (int64_t)ctx->cus * tu.lane_per_cu;
     p.lane_grid = (int32_t)(lg < items ? lg : items);
+    p.lane_block = tu.lane_block == 8 ? 8 : 16;
     p.wave_grid = tu.wave_grid > 0 ? tu.wave_grid : 65536;
     p.maxn = maxn;
     return p;
@@ -508,6 +509,7 @@ split_status enqueue_kernels(split_ctx *ctx, const Instance &in, const EvalBuffe
     ea.ctl = b.d_ctl;
     ea.lane_bytes = p.lane_bytes;
     ea.lane_grid = p.lane_grid;
+    ea.lane_block = p.lane_block;
     ea.wave_grid = p.wave_grid;
     ea.maxn = p.maxn;
 
@@ -612,6 +614,8 @@ split_status check_tuning(split_ctx *ctx, const split_tuning &t)
     if (t.order != 0 && t.order != 1)
         return fail(ctx, SPLIT_E_INVAL, "tuning: order must be 0 or 1");
     if (t.wave_grid < 0) return fail(ctx, SPLIT_E_INVAL, "tuning: wave_grid must be >= 0");
+    if (t.lane_block != 0 && t.lane_block != 8 && t.lane_block != 16)
+        return fail(ctx, SPLIT_E_INVAL, "tuning: lane_block must be 0, 8 or 16");
     return SPLIT_OK;
 }
 
@@ -984,16 +988,54 @@ split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t 
         return split_batch_stats_get(ctx, nullptr, nullptr);
     };
 
+    // scenarios left to the wave kernel, over the first s_eval scenarios, under tuning c
+    std::vector<split_stats> fb_stats((size_t)T);
+    auto fallbacks = [&](const split_tuning &c, int64_t s_eval, int64_t *n) -> split_status {
+        ctx->tuning = c;
+        split_status s = eval_batch(ctx, "split_autotune", tours, tour_ptr, T, demand, s_eval, ld,
+                                    Q, cost, ldc, stream);
+        if (s != SPLIT_OK) return s;
+        s = split_batch_stats_get(ctx, fb_stats.data(), nullptr);
+        if (s != SPLIT_OK) return s;
+        *n = 0;
+        for (const split_stats &x : fb_stats) *n += x.n_fallback;
+        return SPLIT_OK;
+    };
+
     split_tuning win = saved;
     double win_ms = 1e300;
-    const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0}, S, ld, Q, T,
-                                      bi.maxn, bi.max_id);
+    const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0, 0}, S, ld, Q,
+                                      T, bi.maxn, bi.max_id);
     if (lane_probe.form == SPLIT_FORM_LANE) {
+        // the block length first (it follows the window lengths, so the demand law), then the
+        // grid and the order with that block length. 8-state blocks hand windows longer than
+        // about 24 positions to the wave kernel, which costs far more than any block saves: a
+        // probe on the first scenarios drops them when they leave more scenarios there.
+        const int64_t s_fb = S < 4096 ? S : 4096;
+        int64_t fb16 = 0, fb8 = 0;
+        st = fallbacks(split_tuning{SPLIT_FORM_LANE, 0, 0, 0, 16}, s_fb, &fb16);
+        if (st != SPLIT_OK) return finish(st);
+        st = fallbacks(split_tuning{SPLIT_FORM_LANE, 0, 0, 0, 8}, s_fb, &fb8);
+        if (st != SPLIT_OK) return finish(st);
+        int32_t block = 16;
+        for (int32_t lb : {16, 8}) {
+            if (lb == 8 && fb8 > fb16) continue;
+            const split_tuning c = {SPLIT_FORM_LANE, 0, 0, 0, lb};
+            double ms = 0.0;
+            st = measure(c, S, &ms);
+            if (st != SPLIT_OK) return finish(st);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = c;
+                block = lb;
+            }
+        }
         const int32_t per_cu[] = {0, 8, 4, 2};
         for (int32_t pc : per_cu)
             for (int32_t order = 0; order < 2; ++order) {
                 if (T == 1 && order == 1) continue;  // one tour: the order is moot
-                const split_tuning c = {SPLIT_FORM_LANE, pc, order, 0};
+                if (pc == 0 && order == 0) continue;  // timed above
+                const split_tuning c = {SPLIT_FORM_LANE, pc, order, 0, block};
                 double ms = 0.0;
                 st = measure(c, S, &ms);
                 if (st != SPLIT_OK) return finish(st);
@@ -1007,12 +1049,12 @@ split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t 
     // run on at most 256 scenarios, scaled to S, is within 1.5x of the best so far.
     const int64_t s_probe = S < 256 ? S : 256;
     double probe_ms = 0.0;
-    st = measure(split_tuning{SPLIT_FORM_WAVE, 0, 0, 0}, s_probe, &probe_ms);
+    st = measure(split_tuning{SPLIT_FORM_WAVE, 0, 0, 0, 0}, s_probe, &probe_ms);
     if (st != SPLIT_OK) return finish(st);
     if (probe_ms * ((double)S / (double)s_probe) < 1.5 * win_ms) {
         const int32_t grids[] = {0, ctx->cus * 8};
         for (int32_t wg : grids) {
-            const split_tuning c = {SPLIT_FORM_WAVE, 0, 0, wg};
+            const split_tuning c = {SPLIT_FORM_WAVE, 0, 0, wg, 0};
             double ms = 0.0;
             st = measure(c, S, &ms);
             if (st != SPLIT_OK) return finish(st);

@@ -104,6 +104,7 @@ struct EvalArgs {
     BatchCtl *ctl;
     uint32_t lane_bytes;     // lane kernel: bytes of demand it may address, <= kRowAbsent
     int32_t lane_grid;       // lane kernel workgroups (>= the work items: one item each)
+    int32_t lane_block;      // lane kernel block length: 16 or 8 states
     int32_t wave_grid;       // wave kernel workgroups of a full evaluation (form wave)
     int32_t maxn;            // bound on the tour lengths (sizes the wave kernel's LDS)
 };

@@ -109,14 +109,18 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 // ------------------------------------------------------------------------- lane kernel
 //
 // One lane = one scenario; a workgroup is one wavefront of 64 scenarios. States 0..n are
-// processed in blocks of kLB = 16 (block c = states 16c .. 16c+15). For state i, Eq. (3)'s
+// processed in blocks of LB states (block c = states LB*c .. LB*c + LB-1), LB = 16 or 8, a
+// launch choice. A block's windows may reach back over the three blocks before it (windows
+// of up to 3 * LB - 1 positions always fit): 16-state blocks suit windows of about 16 to 47
+// positions; shorter windows mostly start inside a 16-state block, which takes the slow
+// state-by-state path, and 8-state blocks keep them in older blocks. For state i, Eq. (3)'s
 // window is [s_i, i-1] with s_i = #{p : P_p < P_i - Q} (Eq. (2); P = prefix loads).
 //
 // LDS per wavefront, every array interleaved by lane:
 //   rec : per block slot c & 3, the pair (minimum of g over block c, minimum of the block
 //         minima strictly between block c and the block being evaluated);
-//   dl  : suffix minima of g inside each of the last 4 blocks, as 16-bit offsets from the
-//         block minimum (row = position & 63);
+//   dl  : suffix minima of g inside each block of the last 64 positions, as 16-bit offsets
+//         from the block minimum (row = position & 63);
 //   pp  : prefix loads P mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword row
 //         k & 31; rows 0 .. kMirror-1 repeated after the ring so that a 6-row read never wraps.
 // The window minimum of a state of block c whose window starts at s in an older block b is
@@ -132,20 +136,29 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 //
 // A window start s is carried as S = (s << 7) | (lane << 1): the dl offset, the pp row, the
 // rec slot and the even base below s take one or two instructions each. The block loop is
-// unrolled four times so that every LDS store has a constant offset.
+// unrolled 64 / LB times so that every LDS store has a constant offset.
 
-constexpr int kLB = 16;         // states per block
 constexpr int kRingPairs = 32;  // prefix-load ring of 64 positions, two per dword
 constexpr int kMirror = 5;      // ring rows repeated after the ring
 
+// Blocks of LB states: kSteps = blocks in the 64-position history (the unroll of the block
+// loop), kLog = log2(LB). The ring, the suffix offsets and the four block records hold every
+// window start of a block that lies at most three blocks back, so 4 * LB <= 64.
+template <int LB>
+struct LaneCfg {
+    static_assert(LB == 16 || LB == 8, "blocks of 16 or 8 states");
+    static constexpr int kSteps = 64 / LB;
+    static constexpr int kLog = LB == 16 ? 4 : 3;
+};
+
 struct __attribute__((aligned(16))) LaneLds {
     uint64_t rec[4][64];
-    uint16_t dl[4 * kLB][64];
+    uint16_t dl[64][64];
     uint32_t pp[kRingPairs + kMirror][64];
 };
 constexpr uint32_t kRecOff = 0;
 constexpr uint32_t kDlOff = sizeof(uint64_t) * 4 * 64;
-constexpr uint32_t kPpOff = kDlOff + sizeof(uint16_t) * 4 * kLB * 64;
+constexpr uint32_t kPpOff = kDlOff + sizeof(uint16_t) * 64 * 64;
 
 // Read-only per-tour arrays (written by the prep kernel, a previous launch): the constant
 // address space lets every uniform read of them be a scalar load.
@@ -169,11 +182,14 @@ __device__ __forceinline__ const lds_char *lds_base(LaneLds &L)
 
 // Window-minimum lookup of a start S (in an older block): the 16-bit suffix offset and the
 // block record; combined later by query_min so that the reads are in flight meanwhile.
+// The record slot (s / LB) & 3, 512 bytes a slot, is bits 9..10 of S >> (log2(LB) - 2).
+template <int LB>
 __device__ __forceinline__ void query_issue(LaneLds &L, int S, uint32_t lane8, uint32_t &dlv,
                                             uint64_t &recv)
 {
+    constexpr int kSh = LaneCfg<LB>::kLog - 2;
     dlv = *(const lds_u16 *)(lds_base(L) + kDlOff + ((uint32_t)S & 0x1FFEu));
-    recv = *(const lds_u64 *)(lds_base(L) + kRecOff + ((((uint32_t)S >> 2) & 0x600u) | lane8));
+    recv = *(const lds_u64 *)(lds_base(L) + kRecOff + ((((uint32_t)S >> kSh) & 0x600u) | lane8));
 }
 __device__ __forceinline__ int query_min(uint32_t dlv, uint64_t recv, int pre)
 {
@@ -218,17 +234,17 @@ __device__ __forceinline__ int exact_start(LaneLds &L, int lane, int S, uint32_t
     return S_of(s, lane);
 }
 
-// Prefix loads of block c (R = c & 3): q[j] is the demand of position 16c + j (zero where a
-// position does not exist). Writes the ring rows of the block and returns the packed
-// thresholds TT[k] = (P_{16c+2k} - Q, P_{16c+2k+1} - Q) mod 2^16.
-template <int R>
-__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint16_t (&q)[kLB],
+// Prefix loads of block c (R = c mod 64/LB): q[j] is the demand of position LB*c + j (zero
+// where a position does not exist). Writes the ring rows of the block and returns the packed
+// thresholds TT[k] = (P_{LB*c+2k} - Q, P_{LB*c+2k+1} - Q) mod 2^16.
+template <int LB, int R>
+__device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint16_t (&q)[LB],
                                             uint32_t QQ, uint32_t &Plast, uint32_t &qor,
-                                            uint32_t (&TT)[kLB / 2])
+                                            uint32_t (&TT)[LB / 2])
 {
     uint32_t prev = Plast;
 #pragma unroll
-    for (int k = 0; k < kLB / 2; ++k) {
+    for (int k = 0; k < LB / 2; ++k) {
         // (q0, q1) packed by one byte permutation, then (q0, q0 + q1): the low half shifted
         // into the high half adds q0 there and leaves the low half alone
         const u16x2 qv = {q[2 * k], q[2 * k + 1]};
@@ -242,7 +258,7 @@ __device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint16_t
         TT[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, PP) -
                                                  __builtin_bit_cast(u16x2, QQ));
         qor |= Qp;  // both halves: the bound below takes the larger
-        constexpr int row0 = 8 * R;
+        constexpr int row0 = (LB / 2) * R;
         L.pp[(row0 + k) & (kRingPairs - 1)][lane] = PP;
         if (((row0 + k) & (kRingPairs - 1)) < kMirror)
             L.pp[((row0 + k) & (kRingPairs - 1)) + kRingPairs][lane] = PP;
@@ -250,23 +266,25 @@ __device__ __forceinline__ void lane_prefix(LaneLds &L, int lane, const uint16_t
     Plast = prev;
 }
 
-__device__ __forceinline__ uint32_t tt_half(const uint32_t (&TT)[kLB / 2], int t)
+template <int LB>
+__device__ __forceinline__ uint32_t tt_half(const uint32_t (&TT)[LB / 2], int t)
 {
     return (t & 1) ? (TT[t >> 1] >> 16) : (TT[t >> 1] & 0xFFFFu);
 }
 
-// Window starts of the states first .. first + 15, one state at a time with an 8-position
+// Window starts of the states first .. first + LB-1, one state at a time with an 8-position
 // lookahead, completed exactly where the lookahead saturated or reached past the last written
-// prefix load (first + 15). States past n (demand 0) get valid starts too. In: Sp = start of
+// prefix load (first + LB-1). States past n (demand 0) get valid starts too. In: Sp = start of
 // state first - 1.
+template <int LB>
 __device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int first,
-                                                    const uint32_t (&TT)[kLB / 2], int Sp,
-                                                    int (&sOut)[kLB])
+                                                    const uint32_t (&TT)[LB / 2], int Sp,
+                                                    int (&sOut)[LB])
 {
     const uint32_t lane4 = (uint32_t)lane << 2;
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-        const uint32_t T = tt_half(TT, t);
+    for (int t = 0; t < LB; ++t) {
+        const uint32_t T = tt_half<LB>(TT, t);
         const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
         const uint32_t d0 = pp_at(L, off, 0), d1 = pp_at(L, off, 1);
         const uint32_t d2 = pp_at(L, off, 2), d3 = pp_at(L, off, 3);
@@ -276,8 +294,8 @@ __device__ __forceinline__ void lane_starts_careful(LaneLds &L, int lane, int fi
         int Sn = base + (int)((__builtin_popcount(a23) + __builtin_popcount(a01)) << 4);
         // A short count (the eighth position expired too) is exact up to its end: every counted
         // position expired, so the walk continues from there. A read past the written prefix
-        // loads (first + 15) may have counted stale positions: the walk starts over from Sp.
-        const bool past = s_of(base) + 7 > first + kLB - 1;
+        // loads (first + LB-1) may have counted stale positions: the walk starts over from Sp.
+        const bool past = s_of(base) + 7 > first + LB - 1;
         const bool redo = (int32_t)a23 < 0 || past;
         if (redo) Sn = exact_start(L, lane, past ? Sp : Sn, T);
         sOut[t] = Sn;
@@ -318,18 +336,19 @@ __device__ __forceinline__ int pair_count(const PairData &p, uint32_t T, uint32_
     return p.base + (int)(cnt << 4);
 }
 
-// Window starts of the states first .. first + 15 from Sp (start of state first - 1) with the
+// Window starts of the states first .. first + LB-1 from Sp (start of state first - 1) with the
 // pair counts; where a count may be short or a read reached past the written prefix loads
-// (first + 15), the block is redone state by state.
+// (first + LB-1), the block is redone state by state.
+template <int LB>
 __device__ __forceinline__ void lane_starts_pairs(LaneLds &L, int lane, int first,
-                                                  const uint32_t (&TT)[kLB / 2], int Sp,
-                                                  int (&sOut)[kLB])
+                                                  const uint32_t (&TT)[LB / 2], int Sp,
+                                                  int (&sOut)[LB])
 {
     const uint32_t lane4 = (uint32_t)lane << 2;
     const int S_in = Sp;
     uint32_t sat = 0;
 #pragma unroll
-    for (int u = 0; u < kLB / 2; ++u) {
+    for (int u = 0; u < LB / 2; ++u) {
         const PairData p = pair_read(L, lane4, Sp);
         uint32_t x0, x1;
         sOut[2 * u] = pair_count<4>(p, TT[u] & 0xFFFFu, x0);
@@ -337,18 +356,19 @@ __device__ __forceinline__ void lane_starts_pairs(LaneLds &L, int lane, int firs
         sat |= x0 | x1;
         Sp = sOut[2 * u + 1];
     }
-    if (__any((int32_t)sat < 0 || (s_of(sOut[kLB - 3]) & ~1) > first + kLB - 12))
-        lane_starts_careful(L, lane, first, TT, S_in, sOut);
+    if (__any((int32_t)sat < 0 || (s_of(sOut[LB - 3]) & ~1) > first + LB - 12))
+        lane_starts_careful<LB>(L, lane, first, TT, S_in, sOut);
 }
 
 // g of state t of a block (t uniform). Written as explicit selects: the compiler would
 // otherwise turn it into an indexed load from a scratch copy of the whole block.
-__device__ __forceinline__ int block_g_at(const int (&gb)[kLB], int t)
+template <int LB>
+__device__ __forceinline__ int block_g_at(const int (&gb)[LB], int t)
 {
     t = __builtin_amdgcn_readfirstlane(t);
     int g = gb[0];
 #pragma unroll
-    for (int k = 1; k < kLB; ++k) {
+    for (int k = 1; k < LB; ++k) {
         int m = __builtin_amdgcn_readfirstlane(-(int)(t == k));
         asm volatile("" : "+s"(m));  // an opaque 0 / -1 mask
         g = (gb[k] & m) | (g & ~m);
@@ -356,24 +376,24 @@ __device__ __forceinline__ int block_g_at(const int (&gb)[kLB], int t)
     return g;
 }
 
-// Block c complete (R = c & 3): suffix minima as 16-bit offsets from the block minimum, and
-// the records of blocks c, c-1, c-2 (bm1, bm2: minima of blocks c-1, c-2).
-template <int R>
-__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, const int (&gb)[kLB],
+// Block c complete (R = c mod 64/LB): suffix minima as 16-bit offsets from the block minimum,
+// and the records of blocks c, c-1, c-2 (bm1, bm2: minima of blocks c-1, c-2).
+template <int LB, int R>
+__device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, const int (&gb)[LB],
                                                int &bm1, int &bm2, bool &ovf)
 {
-    int sm[kLB];
-    sm[kLB - 1] = gb[kLB - 1];
+    int sm[LB];
+    sm[LB - 1] = gb[LB - 1];
 #pragma unroll
-    for (int t = kLB - 2; t >= 0; --t) sm[t] = min(sm[t + 1], gb[t]);
+    for (int t = LB - 2; t >= 0; --t) sm[t] = min(sm[t + 1], gb[t]);
     const int bm = sm[0];
-    ovf |= (unsigned)(sm[kLB - 1] - bm) > 0xFFFFu;  // the largest offset is the last one
+    ovf |= (unsigned)(sm[LB - 1] - bm) > 0xFFFFu;  // the largest offset is the last one
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) L.dl[kLB * R + t][lane] = (uint16_t)(sm[t] - bm);
+    for (int t = 0; t < LB; ++t) L.dl[LB * R + t][lane] = (uint16_t)(sm[t] - bm);
     auto pack = [](int lo, int hi) {
         return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
     };
-    L.rec[R][lane] = pack(bm, kInf);
+    L.rec[R & 3][lane] = pack(bm, kInf);
     L.rec[(R + 3) & 3][lane] = pack(bm1, bm);
     L.rec[(R + 2) & 3][lane] = pack(bm2, min(bm, bm1));
     bm2 = bm1;
@@ -382,21 +402,22 @@ __device__ __forceinline__ void lane_block_end(LaneLds &L, int lane, const int (
 
 // DP of block c, state by state, for any window position (inside the block, or empty).
 // States past n (demand 0, weight 0) are evaluated too and not used.
+template <int LB>
 __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
                                                 ci32 *__restrict__ w,
-                                                const int (&sCur)[kLB], int (&gb)[kLB], bool &err)
+                                                const int (&sCur)[LB], int (&gb)[LB], bool &err)
 {
-    const int p0 = c * kLB;
+    const int p0 = c * LB;
     const uint32_t lane8 = (uint32_t)lane << 3;
     // every state's older-block lookup, issued up front (in bounds for any start; a lane whose
     // window lies inside the block does not use its result)
-    uint32_t qd[kLB];
-    uint64_t qr[kLB];
+    uint32_t qd[LB];
+    uint64_t qr[LB];
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) query_issue(L, sCur[t], lane8, qd[t], qr[t]);
+    for (int t = 0; t < LB; ++t) query_issue<LB>(L, sCur[t], lane8, qd[t], qr[t]);
     int pre = kInf;
 #pragma unroll
-    for (int t = 0; t < kLB; ++t) {
+    for (int t = 0; t < LB; ++t) {
         const int i = p0 + t;
         int g;
         if (i == 0) {
@@ -428,24 +449,26 @@ __device__ __forceinline__ void lane_dp_careful(LaneLds &L, int lane, int c,
 // Demands of block blk, by buffer loads: the descriptor holds the demand base, the row's byte
 // offset is the scalar offset and the lane's scenario offset the vector one. rowoff is padded
 // past n with a valid row, so blocks past n load unguarded (their values are not used).
+template <int LB>
 __device__ __forceinline__ void lane_load_block(__amdgpu_buffer_rsrc_t rsrc,
                                                 cu32 *__restrict__ rowoff,
-                                                uint32_t lane_off, int blk, uint16_t (&q)[kLB])
+                                                uint32_t lane_off, int blk, uint16_t (&q)[LB])
 {
 #pragma unroll
-    for (int t = 0; t < kLB; ++t)
-        q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * kLB + t], 0);
+    for (int t = 0; t < LB; ++t)
+        q[t] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)rowoff[blk * LB + t], 0);
 }
 
-// The 16 weights of block blk by vector loads (every lane the same 16 bytes, four times): a
+// The LB weights of block blk by vector loads (every lane the same 16 bytes, LB / 4 times): a
 // scalar load here would need a wait that also drains every outstanding LDS operation.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void lane_load_w(__amdgpu_buffer_rsrc_t wrsrc, int blk, int (&wv)[kLB])
+template <int LB>
+__device__ __forceinline__ void lane_load_w(__amdgpu_buffer_rsrc_t wrsrc, int blk, int (&wv)[LB])
 {
 #pragma unroll
-    for (int j = 0; j < kLB / 4; ++j) {
+    for (int j = 0; j < LB / 4; ++j) {
         const i32x4 v = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                       wrsrc, 0, (blk * kLB + 4 * j) * 4, 0));
+                                                       wrsrc, 0, (blk * LB + 4 * j) * 4, 0));
         wv[4 * j] = v.x;
         wv[4 * j + 1] = v.y;
         wv[4 * j + 2] = v.z;
@@ -461,58 +484,58 @@ struct LaneState {
     bool err, ovf;
 };
 
-// One block step (R = c & 3): demands of block c + 3, window starts of block c + 1, DP of
-// block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 3.
-template <int R>
+// One block step (R = c mod 64/LB): demands of block c + 3, window starts of block c + 1, DP
+// of block c. qUse holds the demands of block c + 1, qLoad receives those of block c + 3.
+template <int LB, int R>
 __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, uint32_t QQ,
                                           __amdgpu_buffer_rsrc_t dem, __amdgpu_buffer_rsrc_t wrsrc,
                                           cu32 *__restrict__ rowoff, uint32_t lane_off,
-                                          ci32 *__restrict__ w, const uint16_t (&qUse)[kLB],
-                                          uint16_t (&qLoad)[kLB], const int (&sCur)[kLB],
-                                          int (&sNext)[kLB], const int (&wUse)[kLB],
-                                          int (&wLoad)[kLB], LaneState &st)
+                                          ci32 *__restrict__ w, const uint16_t (&qUse)[LB],
+                                          uint16_t (&qLoad)[LB], const int (&sCur)[LB],
+                                          int (&sNext)[LB], const int (&wUse)[LB],
+                                          int (&wLoad)[LB], LaneState &st)
 {
     // weights of block c + 1 (used by the next step), demands of block c + 3; unconditional,
     // so that every path has the same vector-memory wait counts
-    lane_load_w(wrsrc, c + 1, wLoad);
-    lane_load_block(dem, rowoff, lane_off, c + 3, qLoad);
-    const int nb = n >> 4;
+    lane_load_w<LB>(wrsrc, c + 1, wLoad);
+    lane_load_block<LB>(dem, rowoff, lane_off, c + 3, qLoad);
+    const int nb = n >> LaneCfg<LB>::kLog;
     if (c > nb) return;
-    const int p0 = c * kLB;
-    const int first = p0 + kLB;  // states of block c + 1
+    const int p0 = c * LB;
+    const int first = p0 + LB;  // states of block c + 1
     const uint32_t lane4 = (uint32_t)lane << 2, lane8 = (uint32_t)lane << 3;
     // the ring and the block records must still hold every window start of block c + 1
-    // (state 16c + 15 exists whenever block c + 1 does)
-    if (c + 1 <= nb) st.ovf |= sCur[kLB - 1] < ((p0 - 2 * kLB) << 7);
-    int gb[kLB];
+    // (state LB*c + LB-1 exists whenever block c + 1 does)
+    if (c + 1 <= nb) st.ovf |= sCur[LB - 1] < ((p0 - 2 * LB) << 7);
+    int gb[LB];
     // states past n (demand 0, weight 0) are evaluated like the others and not used
-    const bool fast = c >= 1 && !__any(sCur[kLB - 1] >= (p0 << 7));
+    const bool fast = c >= 1 && !__any(sCur[LB - 1] >= (p0 << 7));
     if (fast) {
-        // Software pipeline over the 8 pairs of block c + 1 and the 16 states of block c.
+        // Software pipeline over the LB/2 pairs of block c + 1 and the LB states of block c.
         // Iteration u: window lookups for the DP of the next pair, DP of states 2u, 2u+1,
         // first state of pair u-1, then second state of pair u (whose read was issued at the
         // end of iteration u-1) and the read of pair u+1. The scheduling barriers keep the
         // independent work between each read and its first use.
         // the block's weights, in vector registers since the previous step
-        int wv[kLB];
+        int wv[LB];
 #pragma unroll
-        for (int t = 0; t < kLB; ++t) wv[t] = wUse[t];
-        uint32_t TT[kLB / 2];
-        lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
-        uint32_t qd[kLB];
-        uint64_t qr[kLB];
-        query_issue(L, sCur[0], lane8, qd[0], qr[0]);
-        query_issue(L, sCur[1], lane8, qd[1], qr[1]);
-        PairData pcur = pair_read(L, lane4, sCur[kLB - 1]);
+        for (int t = 0; t < LB; ++t) wv[t] = wUse[t];
+        uint32_t TT[LB / 2];
+        lane_prefix<LB, (R + 1) % LaneCfg<LB>::kSteps>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
+        uint32_t qd[LB];
+        uint64_t qr[LB];
+        query_issue<LB>(L, sCur[0], lane8, qd[0], qr[0]);
+        query_issue<LB>(L, sCur[1], lane8, qd[1], qr[1]);
+        PairData pcur = pair_read(L, lane4, sCur[LB - 1]);
         PairData pprev = pcur;
         uint32_t sat = 0;  // sign bit: some count of this lane may be short
         int pre = kInf;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < kLB / 2; ++u) {
-            if (u + 1 < kLB / 2) {
-                query_issue(L, sCur[2 * u + 2], lane8, qd[2 * u + 2], qr[2 * u + 2]);
-                query_issue(L, sCur[2 * u + 3], lane8, qd[2 * u + 3], qr[2 * u + 3]);
+        for (int u = 0; u < LB / 2; ++u) {
+            if (u + 1 < LB / 2) {
+                query_issue<LB>(L, sCur[2 * u + 2], lane8, qd[2 * u + 2], qr[2 * u + 2]);
+                query_issue<LB>(L, sCur[2 * u + 3], lane8, qd[2 * u + 3], qr[2 * u + 3]);
             }
 #pragma unroll
             for (int t = 2 * u; t < 2 * u + 2; ++t) {
@@ -531,39 +554,40 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
             sNext[2 * u + 1] = pair_count<6>(pcur, TT[u] >> 16, x1);
             sat |= x1;
             pprev = pcur;
-            if (u + 1 < kLB / 2) pcur = pair_read(L, lane4, sNext[2 * u + 1]);
+            if (u + 1 < LB / 2) pcur = pair_read(L, lane4, sNext[2 * u + 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
         {
             uint32_t x;
-            sNext[kLB - 2] = pair_count<4>(pprev, TT[kLB / 2 - 1] & 0xFFFFu, x);
+            sNext[LB - 2] = pair_count<4>(pprev, TT[LB / 2 - 1] & 0xFFFFu, x);
             sat |= x;
         }
         // no later block reads the last block's records (and its suffix offsets would hold
         // g_n = f_n, which need not fit 16 bits)
-        if (c < nb) lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
+        if (c < nb) lane_block_end<LB, R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
         // the last pair read positions up to its base + 11; the ring is written up to
-        // first + 15. Either condition below is rare: redo the block's starts state by state.
-        if (__any((int32_t)sat < 0 || (s_of(sNext[kLB - 3]) & ~1) > first + kLB - 12))
-            lane_starts_careful(L, lane, first, TT, sCur[kLB - 1], sNext);
-        if (c == nb) st.gres = block_g_at(gb, n & (kLB - 1));
+        // first + LB-1. Either condition below is rare: redo the block's starts state by state.
+        if (__any((int32_t)sat < 0 || (s_of(sNext[LB - 3]) & ~1) > first + LB - 12))
+            lane_starts_careful<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
+        if (c == nb) st.gres = block_g_at<LB>(gb, n & (LB - 1));
         return;
     }
     // careful step (positions past n load demand 0)
     if (c + 1 <= nb) {
-        uint32_t TT[kLB / 2];
-        lane_prefix<(R + 1) & 3>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
-        lane_starts_pairs(L, lane, first, TT, sCur[kLB - 1], sNext);
+        uint32_t TT[LB / 2];
+        lane_prefix<LB, (R + 1) % LaneCfg<LB>::kSteps>(L, lane, qUse, QQ, st.Plast, st.qor, TT);
+        lane_starts_pairs<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
     }
-    lane_dp_careful(L, lane, c, w, sCur, gb, st.err);
+    lane_dp_careful<LB>(L, lane, c, w, sCur, gb, st.err);
     if (c + 1 <= nb) {
-        lane_block_end<R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
+        lane_block_end<LB, R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
     } else {
-        st.gres = block_g_at(gb, n & (kLB - 1));  // block c holds state n
+        st.gres = block_g_at<LB>(gb, n & (LB - 1));  // block c holds state n
     }
 }
 
 // One work item: the 64 scenarios sb*64 .. sb*64+63 of tour t.
+template <int LB>
 __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, long long sb,
                                           __amdgpu_buffer_rsrc_t rsrc)
 {
@@ -592,34 +616,40 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
     st.err = false;
     st.ovf = false;
 
-    const int nb = n >> 4;
-    uint16_t qA[kLB], qB[kLB], qC[kLB], qD[kLB];
-    int sA[kLB], sB[kLB];
-    int wA[kLB], wB[kLB];  // weights of the block a step evaluates, loaded one step ahead
+    const int nb = n >> LaneCfg<LB>::kLog;
+    uint16_t qA[LB], qB[LB], qC[LB], qD[LB];
+    int sA[LB], sB[LB];
+    int wA[LB], wB[LB];  // weights of the block a step evaluates, loaded one step ahead
     const __amdgpu_buffer_rsrc_t wrsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(a.tour.w + ab), (short)0, (int)(sizeof(int32_t) * (n + 1 + kRowPad)), 0x00020000);
 #pragma unroll
-    for (int k = 0; k < kLB; ++k) {
+    for (int k = 0; k < LB; ++k) {
         sA[k] = S_of(0, lane);
         sB[k] = S_of(0, lane);
     }
-    lane_load_w(wrsrc, 0, wA);
-    lane_load_block(rsrc, rowoff, lane_off, 0, qA);
-    lane_load_block(rsrc, rowoff, lane_off, 1, qB);
-    lane_load_block(rsrc, rowoff, lane_off, 2, qC);
+    lane_load_w<LB>(wrsrc, 0, wA);
+    lane_load_block<LB>(rsrc, rowoff, lane_off, 0, qA);
+    lane_load_block<LB>(rsrc, rowoff, lane_off, 1, qB);
+    lane_load_block<LB>(rsrc, rowoff, lane_off, 2, qC);
     {
         // block 0: position 0 has no demand (P_0 = 0, its row offset is absent); start 0
-        uint32_t TT[kLB / 2];
-        lane_prefix<0>(L, lane, qA, QQ, st.Plast, st.qor, TT);
-        lane_starts_pairs(L, lane, 0, TT, S_of(0, lane), sA);
+        uint32_t TT[LB / 2];
+        lane_prefix<LB, 0>(L, lane, qA, QQ, st.Plast, st.qor, TT);
+        lane_starts_pairs<LB>(L, lane, 0, TT, S_of(0, lane), sA);
     }
-    // block b's demands live in q[A, B, C, D][b & 3] and the starts rotate between sA and sB;
-    // four steps per iteration keep these roles and the ring rows of every step constant
-    for (int c = 0; c <= nb; c += 4) {
-        lane_step<0>(L, lane, c, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qB, qD, sA, sB, wA, wB, st);
-        lane_step<1>(L, lane, c + 1, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qC, qA, sB, sA, wB, wA, st);
-        lane_step<2>(L, lane, c + 2, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qD, qB, sA, sB, wA, wB, st);
-        lane_step<3>(L, lane, c + 3, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qA, qC, sB, sA, wB, wA, st);
+    // block b's demands live in q[A, B, C, D][b & 3], its starts and weights in [A, B][b & 1];
+    // 64 / LB steps per iteration keep these roles and the LDS rows of every step constant
+    for (int c = 0; c <= nb; c += LaneCfg<LB>::kSteps) {
+        lane_step<LB, 0>(L, lane, c, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qB, qD, sA, sB, wA, wB, st);
+        lane_step<LB, 1>(L, lane, c + 1, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qC, qA, sB, sA, wB, wA, st);
+        lane_step<LB, 2>(L, lane, c + 2, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qD, qB, sA, sB, wA, wB, st);
+        lane_step<LB, 3>(L, lane, c + 3, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qA, qC, sB, sA, wB, wA, st);
+        if constexpr (LaneCfg<LB>::kSteps == 8) {
+            lane_step<LB, 4>(L, lane, c + 4, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qB, qD, sA, sB, wA, wB, st);
+            lane_step<LB, 5>(L, lane, c + 5, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qC, qA, sB, sA, wB, wA, st);
+            lane_step<LB, 6>(L, lane, c + 6, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qD, qB, sA, sB, wA, wB, st);
+            lane_step<LB, 7>(L, lane, c + 7, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qA, qC, sB, sA, wB, wA, st);
+        }
     }
 
     // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
@@ -643,6 +673,7 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
 // runs item b, then takes items gridDim.x, gridDim.x + 1, ... from a queue until none is left
 // (a grid of at least T * nsb workgroups runs one item each and never touches the queue). The
 // next item's index is fetched while the current one runs.
+template <int LB>
 __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
 {
     __shared__ LaneLds L;
@@ -662,7 +693,7 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
         }
         const long long r = (long long)k / nsb;
         const int t = ((ci32 *)a.tour.order)[r];
-        lane_item(L, a, t, (long long)k - r * nsb, rsrc);
+        lane_item<LB>(L, a, t, (long long)k - r * nsb, rsrc);
         k = __builtin_amdgcn_readfirstlane(knext);
     }
 }
@@ -988,7 +1019,12 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t stream)
 
 hipError_t launch_lane(const EvalArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(split_lane_kernel, dim3((unsigned)a.lane_grid), dim3(64), 0, stream, a);
+    if (a.lane_block == 8)
+        hipLaunchKernelGGL(split_lane_kernel<8>, dim3((unsigned)a.lane_grid), dim3(64), 0, stream,
+                           a);
+    else
+        hipLaunchKernelGGL(split_lane_kernel<16>, dim3((unsigned)a.lane_grid), dim3(64), 0,
+                           stream, a);
     return hipGetLastError();
 }
 

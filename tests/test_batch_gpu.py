@@ -171,7 +171,7 @@ def test_every_tail_length_stays_in_the_lane_kernel(ctx):
 def test_seeded_random_batches_under_launch_choices(ctx, k):
     # random batches (uneven subset tours, some of a single customer) under a different launch
     # choice each: one workgroup per item or a persistent queue, longest-first or given order,
-    # the lane or the wave form; every tour matches the oracle
+    # 16- or 8-state blocks, the lane or the wave form; every tour matches the oracle
     import paper_2511_18022_amd as sg
     rng = np.random.default_rng(7000 + k)
     N = int(rng.integers(2, 300))
@@ -181,14 +181,14 @@ def test_seeded_random_batches_under_launch_choices(ctx, k):
     Q = int(rng.integers(60, 600))
     dem = np.clip(gen.demand_uniform(7000 + k, N, S, 0, Q // int(rng.integers(3, 30))), 0, Q)
     tours = [gen.tour(7000 + k, N, int(rng.integers(1, N + 1)), variant=v) for v in range(T)]
-    choices = [(sg.FORM_LANE, 0, 0), (sg.FORM_LANE, 8, 1), (sg.FORM_LANE, 2, 0),
-               (sg.FORM_LANE, 1, 1), (sg.FORM_WAVE, 0, 0), (sg.FORM_LANE, 4, 0),
-               (sg.FORM_LANE, 0, 1), (sg.FORM_WAVE, 0, 1)]
-    form, per_cu, order = choices[k]
+    choices = [(sg.FORM_LANE, 0, 0, 0), (sg.FORM_LANE, 8, 1, 8), (sg.FORM_LANE, 2, 0, 16),
+               (sg.FORM_LANE, 1, 1, 8), (sg.FORM_WAVE, 0, 0, 0), (sg.FORM_LANE, 4, 0, 8),
+               (sg.FORM_LANE, 0, 1, 8), (sg.FORM_WAVE, 0, 1, 0)]
+    form, per_cu, order, block = choices[k]
     print(f"[batch] random case {k}: N={N} S={S} T={T} Q={Q} form {form} per_cu {per_cu} "
-          f"order {order}", flush=True)
+          f"order {order} lane_block {block}", flush=True)
     ctx.set_coords(xy)
-    ctx.set_tuning(sg.SplitTuning(form, per_cu, order, 0))
+    ctx.set_tuning(sg.SplitTuning(form, per_cu, order, 0, block))
     try:
         check_batch(ctx, tours, np.ascontiguousarray(dem.astype(np.int16)), Q,
                     oracle.dist_matrix(xy), form={sg.FORM_LANE: "lane", sg.FORM_WAVE: "wave"}[form])

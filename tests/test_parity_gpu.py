@@ -3,6 +3,10 @@
 Every cost is an exact integer, so the bar is equality of every scenario's cost, of the
 exact moments, and of the mean and variance doubles (both sides use the same exact
 integers and the same operation order). Inputs are seeded and synthetic (see gen/).
+
+Forms: "lane" is the scenario-per-lane kernel with 16-state blocks, "lane8" the same kernel
+with 8-state blocks, "wave" the wavefront-per-scenario kernel, "mask" the two-kernel form,
+"auto" the library's own choice.
 """
 import os
 
@@ -28,12 +32,21 @@ def ctx():
     c.close()
 
 
+def set_form(ctx, form):
+    import paper_2511_18022_amd as sg
+    if form == "lane8":
+        ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, lane_block=8))
+    else:
+        ctx.set_tuning(sg.SplitTuning())
+        ctx.set_form(form)
+
+
 def run_gpu(ctx, tour, dem_np, Q, form="auto", S=None, xy=None, d=None, ld=None):
     if xy is not None:
         ctx.set_coords(xy)
     if d is not None:
         ctx.set_dist(d)
-    ctx.set_form(form)
+    set_form(ctx, form)
     N, S0 = dem_np.shape
     S = S0 if S is None else S
     if ld is not None and ld > S0:
@@ -63,7 +76,7 @@ WORKLOADS_SMALL = ["uniform-n20", "poisson-n200"]
 
 
 @pytest.mark.parametrize("name", WORKLOADS_SMALL)
-@pytest.mark.parametrize("form", ["lane", "wave", "auto", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "auto", "mask"])
 def test_named_workloads_full_size(ctx, name, form):
     w = gen.make_workload(name)
     print(f"[parity] {name} S={w.S} form={form}", flush=True)
@@ -81,7 +94,7 @@ def test_copula_n1000_full_size_all_scenarios(ctx, form):
 
 
 @pytest.mark.parametrize("S", [1, 2, 63, 64, 65, 1037, 4097])
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 def test_ragged_scenario_counts(ctx, S, form):
     w = gen.make_workload("copula-n1000", S=S)
     n = 300
@@ -90,7 +103,8 @@ def test_ragged_scenario_counts(ctx, S, form):
     check_against_oracle(ctx, tour, w.demand, 500, d, form=form, xy=w.xy)
 
 
-@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 31, 32, 33, 47, 48, 49, 64, 65, 97])
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 15, 16, 17, 23, 24, 25, 31, 32, 33, 47, 48, 49, 64,
+                               65, 97])
 def test_short_and_block_boundary_tours(ctx, n):
     rng = np.random.default_rng(100 + n)
     N = 120
@@ -98,19 +112,20 @@ def test_short_and_block_boundary_tours(ctx, n):
     d = oracle.dist_matrix(xy)
     tour = rng.permutation(np.arange(1, N + 1))[:n].astype(np.int32)
     dem = gen.demand_uniform(9, N, 333, 0, 60)
-    for form in ("lane", "wave"):
+    for form in ("lane", "lane8", "wave"):
         check_against_oracle(ctx, tour, dem, 150, d, form=form, xy=xy)
 
 
-def test_padded_leading_dimension(ctx):
+@pytest.mark.parametrize("form", ["lane", "lane8"])
+def test_padded_leading_dimension(ctx, form):
     w = gen.make_workload("poisson-n200", S=3000)
     d = oracle.dist_matrix(w.xy)
-    got, _ = run_gpu(ctx, w.tour, w.demand, w.Q, form="lane", xy=w.xy, ld=3000 + 77)
+    got, _ = run_gpu(ctx, w.tour, w.demand, w.Q, form=form, xy=w.xy, ld=3000 + 77)
     want = oracle.split(w.tour, d, w.demand, w.Q, threads=ORACLE_THREADS)
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 def test_asymmetric_user_matrix_and_subset_tour(ctx, form):
     rng = np.random.default_rng(7)
     N = 400
@@ -121,7 +136,7 @@ def test_asymmetric_user_matrix_and_subset_tour(ctx, form):
     check_against_oracle(ctx, tour, dem, 300, dmat, form=form, d=dmat)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 def test_long_zero_demand_runs_take_the_general_kernel(ctx, form):
     # windows far longer than the lane kernel's LDS history: the lane kernel must queue these
     # scenarios for the general kernel and the results must stay exact
@@ -137,11 +152,11 @@ def test_long_zero_demand_runs_take_the_general_kernel(ctx, form):
         dem[lo:lo + int(rng.integers(60, 200)), c] = 0
     dem[:, zero_cols[:20]] = 0  # whole scenarios without demand: one route
     _, st = check_against_oracle(ctx, tour, dem, 200, d, form=form, xy=xy)
-    if form == "lane":
+    if form in ("lane", "lane8"):
         assert st.n_fallback > 0
 
 
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 @pytest.mark.parametrize("bad", ["over_capacity", "negative"])
 def test_infeasible_demand_is_reported(ctx, form, bad):
     import paper_2511_18022_amd as sg
@@ -149,7 +164,7 @@ def test_infeasible_demand_is_reported(ctx, form, bad):
     dem = w.demand.copy()
     dem[int(w.tour[7]) - 1, 123] = 101 if bad == "over_capacity" else -3
     ctx.set_coords(w.xy)
-    ctx.set_form(form)
+    set_form(ctx, form)
     with pytest.raises(sg.SplitError) as ei:
         ctx.eval(w.tour, torch.from_numpy(dem).cuda(), w.Q)
     assert ei.value.status == sg.SPLIT_E_DEMAND
@@ -197,7 +212,8 @@ def test_maximum_capacity_and_run_twice_determinism(ctx):
     dem60 = np.ascontiguousarray(np.minimum(w.demand, 60))
     c, _ = check_against_oracle(ctx, w.tour, dem60, 60, d, form="lane", xy=w.xy)
     c2, _ = run_gpu(ctx, w.tour, dem60, 60, form="wave", xy=w.xy)
-    assert np.array_equal(c, c2)
+    c3, _ = run_gpu(ctx, w.tour, dem60, 60, form="lane8", xy=w.xy)
+    assert np.array_equal(c, c2) and np.array_equal(c, c3)
 
 
 def test_maximum_instance_and_tour_length(ctx):
@@ -208,7 +224,7 @@ def test_maximum_instance_and_tour_length(ctx):
     dem = gen.demand_uniform(71, N, 1100, 1, 40)
     tour = gen.tour(71, N, N)
     d = oracle.dist_matrix(xy)
-    for form in ("lane", "wave"):
+    for form in ("lane", "lane8", "wave"):
         print(f"[parity] n = N = {N}, S = 1100, form {form}", flush=True)
         check_against_oracle(ctx, tour, dem, 500, d, form=form, xy=xy)
     with pytest.raises(sg.SplitError) as ei:
@@ -216,7 +232,7 @@ def test_maximum_instance_and_tour_length(ctx):
     assert ei.value.status == sg.SPLIT_E_INVAL
 
 
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 @pytest.mark.parametrize("Q,lo,hi", [(16383, 4000, 16383), (16383, 1, 16383), (4681, 2000, 4681),
                                      (3000, 0, 400)])
 def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi):
@@ -263,7 +279,7 @@ def test_negative_demand_reported_at_capacity_beyond_int16(ctx, form):
     dem = w.demand.copy()
     dem[int(w.tour[3]) - 1, 77] = -1
     ctx.set_coords(w.xy)
-    ctx.set_form(form)
+    set_form(ctx, form)
     with pytest.raises(sg.SplitError) as ei:
         ctx.eval(w.tour, torch.from_numpy(dem).cuda(), 40000)
     assert ei.value.status == sg.SPLIT_E_DEMAND
@@ -273,7 +289,7 @@ def test_async_calls_and_stats_get(ctx):
     w = gen.make_workload("poisson-n200", S=10000)
     d = oracle.dist_matrix(w.xy)
     ctx.set_coords(w.xy)
-    ctx.set_form("lane")
+    set_form(ctx, "lane")
     dem = torch.from_numpy(w.demand).cuda()
     outs = []
     for k in range(3):
@@ -324,7 +340,7 @@ def test_seeded_random_instances_all_forms(ctx, k):
     d = oracle.dist_matrix(xy)
     print(f"[parity] random case {k}: N={len(xy) - 1} n={len(tour)} S={dem.shape[1]} Q={Q}",
           flush=True)
-    for form in ("lane", "wave", "mask"):
+    for form in ("lane", "lane8", "wave", "mask"):
         check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
 
 
@@ -332,7 +348,7 @@ def test_kernel_timing_totals_and_samples(ctx):
     # the bench's dominant-kernel timing: one sample per timed evaluation, summing to the total
     w = gen.make_workload("poisson-n200", S=5000)
     ctx.set_coords(w.xy)
-    ctx.set_form("lane")
+    set_form(ctx, "lane")
     dem = torch.from_numpy(w.demand).cuda()
     ctx.timing(True)
     ctx.timing_reset()

@@ -41,8 +41,8 @@ def test_every_launch_choice_gives_the_oracle_costs(sg, batch):
     b, d, want = batch
     ctx = fresh_ctx(sg, b.xy)
     dem = torch.from_numpy(b.demand).cuda()
-    choices = [sg.SplitTuning(sg.FORM_LANE, pc, order, 0)
-               for pc in (0, 1, 2, 4, 8) for order in (0, 1)]
+    choices = [sg.SplitTuning(sg.FORM_LANE, pc, order, 0, lb)
+               for lb in (0, 8) for pc in (0, 1, 2, 4, 8) for order in (0, 1)]
     choices += [sg.SplitTuning(sg.FORM_WAVE, 0, 0, wg) for wg in (0, 1024)]
     for tu in choices:
         print(f"[tuning] {tu}", flush=True)
@@ -62,7 +62,8 @@ def test_tuning_fields_are_checked(sg, batch):
     ctx = fresh_ctx(sg, b.xy)
     for bad in (sg.SplitTuning(7, 0, 0, 0), sg.SplitTuning(1, 9, 0, 0),
                 sg.SplitTuning(1, -1, 0, 0), sg.SplitTuning(1, 0, 2, 0),
-                sg.SplitTuning(2, 0, 0, -5)):
+                sg.SplitTuning(2, 0, 0, -5), sg.SplitTuning(1, 0, 0, 0, 4),
+                sg.SplitTuning(1, 0, 0, 0, 12)):
         with pytest.raises(sg.SplitError) as ei:
             ctx.set_tuning(bad)
         assert ei.value.status == sg.SPLIT_E_INVAL
@@ -99,6 +100,27 @@ def test_autotune_small_scenario_count_considers_the_wave_form(sg):
     tu, ms, cost = ctx.autotune([w.tour], dem, w.Q, reps=3)
     print(f"[autotune] uniform-n20: {tu} {ms:.4f} ms", flush=True)
     assert np.array_equal(cost.cpu().numpy()[0], oracle.split(w.tour, d, w.demand, w.Q))
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,block", [("poisson-n200", 8), ("copula-n1000", 16)])
+def test_autotune_block_length_follows_the_window_lengths(sg, name, block):
+    # windows of about 13 positions (poisson-n200) mostly start inside 16-state blocks: 8-state
+    # blocks keep them in older blocks and win. Windows of about 24 (copula-n1000) outgrow
+    # three 8-state blocks: the fallback probe drops 8 and 16 stays.
+    w = gen.make_workload(name, S=65536, threads=ORACLE_THREADS)
+    ctx = fresh_ctx(sg, w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    tu, ms, cost = ctx.autotune([w.tour], dem, w.Q, reps=5)
+    print(f"[autotune] {name}: {tu} {ms:.4f} ms", flush=True)
+    assert tu.form == sg.FORM_LANE and tu.lane_block == block
+    _, stats, _ = ctx.eval_batch([w.tour], dem, w.Q)
+    assert stats[0].n_fallback == 0
+    # the costs under the choice, on a sample against the oracle
+    idx = np.random.default_rng(5).choice(w.S, size=2048, replace=False)
+    want = oracle.split(w.tour, oracle.dist_matrix(w.xy),
+                        np.ascontiguousarray(w.demand[:, idx]), w.Q, threads=ORACLE_THREADS)
+    assert np.array_equal(cost.cpu().numpy()[0, idx], want)
     ctx.close()
 
 
