@@ -165,6 +165,37 @@ def test_graph_replays_match_eager_evaluations(sg, batch):
     ctx.close()
 
 
+def test_graph_with_8_state_blocks_and_the_persistent_queue(sg):
+    # the graph captures the context's launch choices: here 8-state blocks and 2 persistent
+    # workgroups per CU, over short-window Poisson demands (the case 8-state blocks are for);
+    # every replay equals an eager evaluation under the same choice and the oracle
+    w = gen.make_workload("poisson-n200", S=20000)
+    d = oracle.dist_matrix(w.xy)
+    ctx = fresh_ctx(sg, w.xy)
+    ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, 2, 0, 0, 8))
+    dem = torch.from_numpy(w.demand).cuda()
+    rng = np.random.default_rng(23)
+    g = ctx.graph(max_T=4, max_total_n=4 * w.N, demand=dem, Q=w.Q)
+    for rep in range(3):
+        T = int(rng.integers(1, 5))
+        tours = [gen.tour(w.seed, w.N, int(rng.integers(1, w.N + 1)), variant=500 + 10 * rep + k)
+                 for k in range(T)]
+        print(f"[graph-lb8] replay {rep}: T={T} lengths={[len(t) for t in tours]}", flush=True)
+        cost = g.launch(tours)
+        gstats, gstatus = g.stats()
+        got = cost[:T].cpu().numpy()
+        ec, estats, estatus = ctx.eval_batch(tours, dem, w.Q)
+        assert np.array_equal(got, ec.cpu().numpy()), f"replay {rep}"
+        assert gstatus == estatus == [0] * T
+        assert [s.sum for s in gstats] == [s.sum for s in estats]
+        assert sum(s.n_fallback for s in gstats) == 0
+        for k, t in enumerate(tours):
+            assert np.array_equal(got[k], oracle.split(t, d, w.demand, w.Q,
+                                                       threads=ORACLE_THREADS)), (rep, k)
+    g.close()
+    ctx.close()
+
+
 def test_graph_back_to_back_launches_keep_each_batch(sg, batch):
     # two launches in flight use the two host slots; each batch's result is read after the
     # stream reaches it
