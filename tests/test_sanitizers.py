@@ -39,10 +39,12 @@ def test_oracle_and_generators_under_asan_ubsan(tmp_path):
     _build(os.path.join(ROOT, "oracle", "oracle.c"), olib, [])
     _build(os.path.join(ROOT, "gen", "gen.c"), glib, ["-lm"])
     env = dict(os.environ)
+    # the sanitizer runtimes go first; anything already preloaded stays after them
+    preload = ":".join(p for p in (asan, ubsan, os.environ.get("LD_PRELOAD", "")) if p)
     env.update({
         "SPLIT_ORACLE_LIB": olib,
         "SPLIT_GEN_LIB": glib,
-        "LD_PRELOAD": f"{asan}:{ubsan}",
+        "LD_PRELOAD": preload,
         # the Python interpreter itself is not instrumented: its allocations are not leaks
         # of ours
         "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1:halt_on_error=1",
