@@ -167,20 +167,29 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
 // Y[t][j + 2][co] for M = T * n positions. A workgroup is 4 wavefronts; each wavefront computes
 // 64 positions x 128 channels: 4 x 8 tiles of 16 x 16, K = 5 * CI in blocks of 32. The weights
 // of one K block (128 co x 32, 8 KB) are staged in LDS once per workgroup, double-buffered with
-// one barrier per block; the activation fragments of the next block are loaded while the
-// current one runs. LDS holds a block as [k quarter][co] so that the 16-byte reads of the 16
-// lanes of a column group hit consecutive addresses.
+// one barrier per block. The global loads of a block's activation fragments and weights are
+// issued kConvDepth blocks before the block runs, into a register ring (the K loop is unrolled
+// so that every ring slot is a fixed register set): at one wavefront per SIMD, a load from the
+// last-level cache takes several blocks' worth of MFMA time. LDS holds a block as
+// [k quarter][co] so that the 16-byte reads of the 16 lanes of a column group hit consecutive
+// addresses.
 // MODE 0: Y = bf16(relu(acc + bias[co]))       (forward)
 // MODE 1: Y = bf16(acc) where mask > 0, else 0 (backward data: mask = the layer's input H)
 // Wavefronts past the last position run the loop on a clamped row (every barrier is reached)
 // and store nothing.
+constexpr int kConvDepth = 4;  // K blocks of global loads in flight
+
 template <int CI, int MODE>
-__global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const uint16_t *Wt,
-                                                      const float *bias, const uint16_t *mask,
-                                                      uint16_t *Y, int32_t T, int32_t n)
+__global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict__ X,
+                                                      const uint16_t *__restrict__ Wt,
+                                                      const float *__restrict__ bias,
+                                                      const uint16_t *__restrict__ mask,
+                                                      uint16_t *__restrict__ Y, int32_t T,
+                                                      int32_t n)
 {
     constexpr int K = kNnTaps * CI;
     constexpr int KB = K / 32;
+    constexpr int D = KB < kConvDepth ? KB : kConvDepth;
     __shared__ bf16x8 Bs[2][4 * kNnWidth];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -208,21 +217,37 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    Bs[0][wdst0] = wsrc0[0];
-    Bs[0][wdst1] = wsrc1[0];
-    bf16x8 a[4];
+    // ring slot q holds the activation fragments and weight chunks of blocks q, q + D, ...
+    bf16x8 ra[D][4], rw[D][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) a[mt] = arow[mt][0];
+    for (int q = 0; q < D; ++q) {
+        rw[q][0] = wsrc0[q * 4];
+        rw[q][1] = wsrc1[q * 4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) ra[q][mt] = arow[mt][q * 4];
+    }
+    Bs[0][wdst0] = rw[0][0];
+    Bs[0][wdst1] = rw[0][1];
     __syncthreads();
+#pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const int cur = kb & 1;
-        const bool more = kb + 1 < KB;
-        bf16x8 wn0, wn1, an[4];
-        if (more) {
-            wn0 = wsrc0[(kb + 1) * 4];
-            wn1 = wsrc1[(kb + 1) * 4];
+        const int slot = kb % D;
+        bf16x8 a[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) an[mt] = arow[mt][(kb + 1) * 4];
+        for (int mt = 0; mt < 4; ++mt) a[mt] = ra[slot][mt];
+        bf16x8 wn0, wn1;  // weights of block kb + 1, staged after this block's products
+        if (kb + 1 < KB) {
+            wn0 = rw[(kb + 1) % D][0];
+            wn1 = rw[(kb + 1) % D][1];
+        }
+        // the slot's weights (block kb) went to LDS one block ago and its fragments are in a[]:
+        // refill it with block kb + D
+        if (kb + D < KB) {
+            rw[slot][0] = wsrc0[(kb + D) * 4];
+            rw[slot][1] = wsrc1[(kb + D) * 4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) ra[slot][mt] = arow[mt][(kb + D) * 4];
         }
         bf16x8 b[8];
 #pragma unroll
@@ -233,47 +258,66 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *X, const u
             for (int nt = 0; nt < 8; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt],
                                                                       0, 0, 0);
-        if (more) {
+        if (kb + 1 < KB) {
             Bs[cur ^ 1][wdst0] = wn0;
             Bs[cur ^ 1][wdst1] = wn1;
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
         }
         __syncthreads();
     }
     if (m0 >= M) return;
     // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile.
     // Row mb + off (off <= 51) is position jb + off of tour tb, carried into the next tours
-    // past their ends: one division per lane.
+    // past their ends: one division per lane. The bias values (MODE 0) are loaded once, and a
+    // tile's 32 mask values (MODE 1) are all requested before the first is used.
     const long long mb = m0 + (lane >> 4) * 4;
     const long long tb = mb / n;
     const int jb = (int)(mb - tb * n);
+    float bco[8];
+    if (MODE == 0) {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+        for (int nt = 0; nt < 8; ++nt) bco[nt] = bias[nt * 16 + r16];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        long long base[4];
+        bool live[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int off = mt * 16 + i;
-            if (mb + off >= M) continue;
+            live[i] = mb + off < M;
             long long t = tb;
             int j = jb + off;
             while (j >= n) {
                 j -= n;
                 ++t;
             }
-            const long long base = (t * (n + 4) + j + 2) * kNnWidth;
+            // a row past the last position addresses row 0 (read only under MODE 1's mask,
+            // never written)
+            base[i] = live[i] ? (t * (n + 4) + j + 2) * kNnWidth : 0;
+        }
+        uint16_t mk[4][8];
+        if (MODE == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int nt = 0; nt < 8; ++nt) mk[i][nt] = mask[base[i] + nt * 16 + r16];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (!live[i]) continue;
 #pragma unroll
             for (int nt = 0; nt < 8; ++nt) {
-                const int co = nt * 16 + r16;
                 float v = acc[mt][nt][i];
                 if (MODE == 0) {
-                    v += bias[co];
+                    v += bco[nt];
                     v = v > 0.f ? v : 0.f;
                 } else {
-                    if (mask[base + co] == 0 || (mask[base + co] & 0x8000u)) v = 0.f;
+                    if (mk[i][nt] == 0 || (mk[i][nt] & 0x8000u)) v = 0.f;
                 }
-                Y[base + co] = bf16_bits_hw(v);
+                Y[base[i] + nt * 16 + r16] = bf16_bits_hw(v);
             }
         }
+    }
 }
 
 // ------------------------------------------------------------------------- fused inference
@@ -546,7 +590,17 @@ __global__ __launch_bounds__(256) void nn_head_fwd_kernel(const uint16_t *H4, in
     const int r = tid >> 4, g = tid & 15;
     const u16x8 *h = reinterpret_cast<const u16x8 *>(H4 + ((long long)t * (n + 4) + 2) * kNnWidth) + g;
     float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int j = r; j < n; j += 16) {
+    int j = r;
+    for (; j + 48 < n; j += 64) {  // rows j, j + 16, j + 32, j + 48: loads first, adds in order
+        u16x8 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = h[(long long)(j + 16 * u) * (kNnWidth / 8)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += bf16_to_f32(v[u][e]);
+    }
+    for (; j < n; j += 16) {
         const u16x8 v = h[(long long)j * (kNnWidth / 8)];
 #pragma unroll
         for (int e = 0; e < 8; ++e) s[e] += bf16_to_f32(v[e]);
@@ -612,14 +666,31 @@ __global__ __launch_bounds__(128) void nn_head_bwd_kernel(const float *labels, i
 
 // Head parameter gradients, summed over the batch in tour order. Grid kNnWidth + 1 workgroups of
 // 128: workgroup o < 128 writes gWa[o][*] and gba[o]; the last writes gwb and gbb.
-__global__ __launch_bounds__(128) void nn_head_grad_kernel(int32_t T, const float *z,
-                                                           const float *a, const float *da,
-                                                           const float *dy, float *G)
+// The sums run in tour order; the loads of 8 tours are issued before their products.
+__global__ __launch_bounds__(128) void nn_head_grad_kernel(int32_t T, const float *__restrict__ z,
+                                                           const float *__restrict__ a,
+                                                           const float *__restrict__ da,
+                                                           const float *__restrict__ dy,
+                                                           float *__restrict__ G)
 {
     const int o = blockIdx.x, i = threadIdx.x;
     if (o < kNnWidth) {
         float s = 0.f, sb = 0.f;
-        for (int t = 0; t < T; ++t) {
+        int t = 0;
+        for (; t + 8 <= T; t += 8) {
+            float d[8], zz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                d[u] = da[(long long)(t + u) * kNnWidth + o];
+                zz[u] = z[(long long)(t + u) * kNnWidth + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s += d[u] * zz[u];
+                sb += d[u];
+            }
+        }
+        for (; t < T; ++t) {
             const float d = da[(long long)t * kNnWidth + o];
             s += d * z[(long long)t * kNnWidth + i];
             sb += d;
@@ -628,7 +699,21 @@ __global__ __launch_bounds__(128) void nn_head_grad_kernel(int32_t T, const floa
         if (i == 0) G[kNnOffBa + o] = sb;
     } else {
         float s = 0.f, sb = 0.f;
-        for (int t = 0; t < T; ++t) {
+        int t = 0;
+        for (; t + 8 <= T; t += 8) {
+            float at[8], dd[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                at[u] = a[(long long)(t + u) * kNnWidth + i];
+                dd[u] = dy[t + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s += dd[u] * (at[u] > 0.f ? at[u] : 0.f);
+                sb += dd[u];
+            }
+        }
+        for (; t < T; ++t) {
             const float at = a[(long long)t * kNnWidth + i];
             s += dy[t] * (at > 0.f ? at : 0.f);
             sb += dy[t];
@@ -638,19 +723,27 @@ __global__ __launch_bounds__(128) void nn_head_grad_kernel(int32_t T, const floa
     }
 }
 
-// dP4[t][j][c] = bf16(dz[t][c] / n) where H4 > 0, else 0 (interior rows only)
-__global__ __launch_bounds__(256) void nn_dp4_kernel(const float *dz, const uint16_t *H4,
-                                                     int32_t T, int32_t n, uint16_t *dP)
+// dP4[t][j][c] = bf16(dz[t][c] / n) where H4 > 0, else 0 (interior rows only); a thread takes
+// 8 consecutive channels of one position (16-byte loads and stores)
+__global__ __launch_bounds__(256) void nn_dp4_kernel(const float *__restrict__ dz,
+                                                     const uint16_t *__restrict__ H4, int32_t T,
+                                                     int32_t n, uint16_t *__restrict__ dP)
 {
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (long long)T * n * kNnWidth) return;
-    const int c = (int)(e % kNnWidth);
-    const long long m = e / kNnWidth;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;  // (position, channel octet)
+    if (e >= (long long)T * n * (kNnWidth / 8)) return;
+    const int c0 = (int)(e % (kNnWidth / 8)) * 8;
+    const long long m = e / (kNnWidth / 8);
     const long long t = m / n, j = m - t * n;
-    const long long idx = (t * (n + 4) + j + 2) * kNnWidth + c;
-    const uint16_t h = H4[idx];
-    const bool on = h != 0 && !(h & 0x8000u);
-    dP[idx] = on ? bf16_bits_f32(dz[t * kNnWidth + c] / (float)n) : (uint16_t)0;
+    const long long idx = (t * (n + 4) + j + 2) * kNnWidth + c0;
+    const u16x8 h = *reinterpret_cast<const u16x8 *>(H4 + idx);
+    const float *dzt = dz + t * kNnWidth + c0;
+    u16x8 out;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool on = h[k] != 0 && !(h[k] & 0x8000u);
+        out[k] = on ? bf16_bits_f32(dzt[k] / (float)n) : (uint16_t)0;
+    }
+    *reinterpret_cast<u16x8 *>(dP + idx) = out;
 }
 
 // ------------------------------------------------------------------------- weight gradients
@@ -759,22 +852,37 @@ __global__ __launch_bounds__(256) void nn_wgrad_kernel(const uint16_t *H, const 
     if (slice == 0 && tid < kNnWidth) partB[(long long)blockIdx.x * kNnWidth + tid] = bsum;
 }
 
+// sum_{k < chunks} p[k * stride] in chunk order, with the loads of 64 chunks issued before
+// their adds (one thread per sum: the time is the latency of these loads). In the last group,
+// slots past the last chunk load that chunk again and add +0.0 instead, which leaves every sum
+// unchanged (a sum that starts at +0.0 is never -0.0).
+__device__ __forceinline__ float sum_chunks(const float *__restrict__ p, long long stride,
+                                            int32_t chunks)
+{
+    float s = 0.f;
+    for (int k = 0; k < chunks; k += 64) {
+        float v[64];
+#pragma unroll
+        for (int u = 0; u < 64; ++u) v[u] = p[(long long)min(k + u, chunks - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < 64; ++u) s += k + u < chunks ? v[u] : 0.f;
+    }
+    return s;
+}
+
 // G[offW + e] = sum over chunks of partW[chunk][e] (e < count), G[offB + c] likewise for the bias
-__global__ __launch_bounds__(256) void nn_wgrad_reduce_kernel(const float *partW,
-                                                              const float *partB, int32_t chunks,
-                                                              int32_t count, float *G, int32_t offW,
+__global__ __launch_bounds__(256) void nn_wgrad_reduce_kernel(const float *__restrict__ partW,
+                                                              const float *__restrict__ partB,
+                                                              int32_t chunks, int32_t count,
+                                                              float *__restrict__ G, int32_t offW,
                                                               int32_t offB)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e < count) {
-        float s = 0.f;
-        for (int k = 0; k < chunks; ++k) s += partW[(long long)k * count + e];
-        G[offW + e] = s;
+        G[offW + e] = sum_chunks(partW + e, count, chunks);
     } else if (e < count + kNnWidth) {
         const int c = e - count;
-        float s = 0.f;
-        for (int k = 0; k < chunks; ++k) s += partB[(long long)k * kNnWidth + c];
-        G[offB + c] = s;
+        G[offB + c] = sum_chunks(partB + c, kNnWidth, chunks);
     }
 }
 
@@ -1115,8 +1223,8 @@ hipError_t nn_launch_head_bwd(const float *labels, int32_t T, int32_t n, const f
                        G);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nn_dp4_kernel, dim3(grid_of((long long)T * n * kNnWidth, 256)), dim3(256),
-                       0, st, dz, H4, T, n, dP4);
+    hipLaunchKernelGGL(nn_dp4_kernel, dim3(grid_of((long long)T * n * (kNnWidth / 8), 256)),
+                       dim3(256), 0, st, dz, H4, T, n, dP4);
     return hipGetLastError();
 }
 
