@@ -166,18 +166,18 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
 
 // Y[t][j + 2][co] for M = T * n positions. A workgroup is 4 wavefronts; each wavefront computes
 // 64 positions x 128 channels: 4 x 8 tiles of 16 x 16, K = 5 * CI in blocks of 32. The weights
-// of one K block (128 co x 32, 8 KB) are staged in LDS once per workgroup, double-buffered with
-// one barrier per block. The global loads of a block's activation fragments and weights are
-// issued kConvDepth blocks before the block runs, into a register ring (the K loop is unrolled
-// so that every ring slot is a fixed register set): at one wavefront per SIMD, a load from the
-// last-level cache takes several blocks' worth of MFMA time. LDS holds a block as
-// [k quarter][co] so that the 16-byte reads of the 16 lanes of a column group hit consecutive
-// addresses.
+// are staged in LDS a group of GB K blocks (GB x 8 KB) at a time, double-buffered, with one
+// barrier per group: the group after next is loaded into registers while a group runs. The
+// activation fragments of a block are loaded kConvDepth blocks before it runs, into a register
+// ring (the K loop is unrolled so that every ring slot is a fixed register set): at one
+// wavefront per SIMD, a load from the last-level cache takes several blocks' worth of MFMA time.
+// LDS holds a block as [k quarter][co] so that the 16-byte reads of the 16 lanes of a column
+// group hit consecutive addresses.
 // MODE 0: Y = bf16(relu(acc + bias[co]))       (forward)
 // MODE 1: Y = bf16(acc) where mask > 0, else 0 (backward data: mask = the layer's input H)
 // Wavefronts past the last position run the loop on a clamped row (every barrier is reached)
 // and store nothing.
-constexpr int kConvDepth = 4;  // K blocks of global loads in flight
+constexpr int kConvDepth = 4;  // K blocks of activation loads in flight
 
 template <int CI, int MODE>
 __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict__ X,
@@ -190,7 +190,10 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict
     constexpr int K = kNnTaps * CI;
     constexpr int KB = K / 32;
     constexpr int D = KB < kConvDepth ? KB : kConvDepth;
-    __shared__ bf16x8 Bs[2][4 * kNnWidth];
+    constexpr int GB = KB % 4 == 0 ? 4 : KB;  // K blocks per staged weight group
+    constexpr int NG = KB / GB;
+    constexpr int BLK = 4 * kNnWidth;         // bf16x8 chunks of one K block
+    __shared__ bf16x8 Bs[2][GB * BLK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -217,52 +220,65 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // ring slot q holds the activation fragments and weight chunks of blocks q, q + D, ...
-    bf16x8 ra[D][4], rw[D][2];
+    // activation ring: slot q holds the fragments of blocks q, q + D, ...
+    bf16x8 ra[D][4];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        rw[q][0] = wsrc0[q * 4];
-        rw[q][1] = wsrc1[q * 4];
+    for (int q = 0; q < D; ++q)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) ra[q][mt] = arow[mt][q * 4];
+    // weight group 0 to LDS; group 1 into registers
+    bf16x8 wr[GB][2];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+        Bs[0][q * BLK + wdst0] = wsrc0[q * 4];
+        Bs[0][q * BLK + wdst1] = wsrc1[q * 4];
     }
-    Bs[0][wdst0] = rw[0][0];
-    Bs[0][wdst1] = rw[0][1];
+    if (NG > 1) {
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+            wr[q][0] = wsrc0[(GB + q) * 4];
+            wr[q][1] = wsrc1[(GB + q) * 4];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-        const int cur = kb & 1;
+        const int g = kb / GB, q = kb % GB, cur = g & 1;
         const int slot = kb % D;
         bf16x8 a[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) a[mt] = ra[slot][mt];
-        bf16x8 wn0, wn1;  // weights of block kb + 1, staged after this block's products
-        if (kb + 1 < KB) {
-            wn0 = rw[(kb + 1) % D][0];
-            wn1 = rw[(kb + 1) % D][1];
-        }
-        // the slot's weights (block kb) went to LDS one block ago and its fragments are in a[]:
-        // refill it with block kb + D
+        // the slot's fragments are in a[]: refill it with block kb + D
         if (kb + D < KB) {
-            rw[slot][0] = wsrc0[(kb + D) * 4];
-            rw[slot][1] = wsrc1[(kb + D) * 4];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) ra[slot][mt] = arow[mt][(kb + D) * 4];
         }
         bf16x8 b[8];
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) b[nt] = Bs[cur][kq * kNnWidth + nt * 16 + r16];
+        for (int nt = 0; nt < 8; ++nt) b[nt] = Bs[cur][q * BLK + kq * kNnWidth + nt * 16 + r16];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 8; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt],
                                                                       0, 0, 0);
-        if (kb + 1 < KB) {
-            Bs[cur ^ 1][wdst0] = wn0;
-            Bs[cur ^ 1][wdst1] = wn1;
+        if (q == GB - 1 && g + 1 < NG) {
+            // group g + 1 to the other buffer (last read in group g - 1, before the previous
+            // barrier), group g + 2 into registers
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                Bs[cur ^ 1][u * BLK + wdst0] = wr[u][0];
+                Bs[cur ^ 1][u * BLK + wdst1] = wr[u][1];
+            }
+            if (g + 2 < NG) {
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    wr[u][0] = wsrc0[((g + 2) * GB + u) * 4];
+                    wr[u][1] = wsrc1[((g + 2) * GB + u) * 4];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (m0 >= M) return;
     // D rows (lane / 16) * 4 + i of each 16-row tile, column lane % 16 of each 16-column tile.
