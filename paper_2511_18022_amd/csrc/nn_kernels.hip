@@ -169,18 +169,19 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
 // are staged in LDS a group of GB K blocks (GB x 8 KB) at a time, double-buffered, with one
 // barrier per group: the group after next is loaded into registers while a group runs. The
 // activation fragments of a block are loaded kConvDepth blocks before it runs, into a register
-// ring (the K loop is unrolled so that every ring slot is a fixed register set): at one
-// wavefront per SIMD, a load from the last-level cache takes several blocks' worth of MFMA time.
+// ring (the K loop is unrolled so that every ring slot is a fixed register set). The register
+// budget (at most 256 per lane) lets two wavefronts share each SIMD, whose MFMA work then
+// covers the other's waits.
 // LDS holds a block as [k quarter][co] so that the 16-byte reads of the 16 lanes of a column
 // group hit consecutive addresses.
 // MODE 0: Y = bf16(relu(acc + bias[co]))       (forward)
 // MODE 1: Y = bf16(acc) where mask > 0, else 0 (backward data: mask = the layer's input H)
 // Wavefronts past the last position run the loop on a clamped row (every barrier is reached)
 // and store nothing.
-constexpr int kConvDepth = 4;  // K blocks of activation loads in flight
+constexpr int kConvDepth = 2;  // K blocks of activation loads in flight
 
 template <int CI, int MODE>
-__global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nn_conv_kernel(const uint16_t *__restrict__ X,
                                                       const uint16_t *__restrict__ Wt,
                                                       const float *__restrict__ bias,
                                                       const uint16_t *__restrict__ mask,
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void nn_conv_kernel(const uint16_t *__restrict
     constexpr int K = kNnTaps * CI;
     constexpr int KB = K / 32;
     constexpr int D = KB < kConvDepth ? KB : kConvDepth;
-    constexpr int GB = KB % 4 == 0 ? 4 : KB;  // K blocks per staged weight group
+    constexpr int GB = KB % 2 == 0 ? 2 : KB;  // K blocks per staged weight group
     constexpr int NG = KB / GB;
     constexpr int BLK = 4 * kNnWidth;         // bf16x8 chunks of one K block
     __shared__ bf16x8 Bs[2][GB * BLK];
