@@ -776,12 +776,14 @@ __global__ __launch_bounds__(256) void nn_dp4_kernel(const float *__restrict__ d
 // and all taps (20 tiles). Slice 0 also sums the bias gradient, thread co over the staged rows
 // in order.
 template <int CI>
-__global__ __launch_bounds__(256) void nn_wgrad_kernel(const uint16_t *H, const uint16_t *dP,
-                                                       long long R, int32_t chunk, float *partW,
-                                                       float *partB)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nn_wgrad_kernel(
+    const uint16_t *__restrict__ H, const uint16_t *__restrict__ dP, long long R, int32_t chunk,
+    float *__restrict__ partW, float *__restrict__ partB)
 {
     constexpr int KR = 64;      // rows per staged block
     constexpr int SK = KR + 8;  // bf16 per transposed LDS row (16 bytes of padding)
+    constexpr int NP = KR * 16 / 256;               // dP chunks per thread and block
+    constexpr int NH = ((KR + 4) * 4 + 255) / 256;  // H chunks per thread and block (at most)
     __shared__ __attribute__((aligned(16))) uint16_t pt[kNnWidth * SK];
     __shared__ __attribute__((aligned(16))) uint16_t ht[kNnTaps * 32 * SK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -795,33 +797,58 @@ __global__ __launch_bounds__(256) void nn_wgrad_kernel(const uint16_t *H, const 
 #pragma unroll
         for (int i = 0; i < 2; ++i) acc[t][i][0] = acc[t][i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
+    // a block's global rows, loaded one block ahead: dP rows rb .. rb + 63 (zero from r1 on),
+    // 16 chunks of 8 channels per row, and H rows rb - 2 .. rb + 65 (rb >= 2; zero past the
+    // last row), 4 chunks of 8 channels of this slice
+    u16x8 dv[NP], hv[NH];
+    auto load_block = [&](long long rb) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int e = tid + 256 * u;
+            const long long r = rb + e % KR;
+            dv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (r < r1)
+                dv[u] = *reinterpret_cast<const u16x8 *>(dP + r * kNnWidth + (e / KR) * 8);
+        }
+#pragma unroll
+        for (int u = 0; u < NH; ++u) {
+            const int e = tid + 256 * u;
+            const long long h = rb - 2 + e % (KR + 4);
+            hv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (e < (KR + 4) * 4 && h < R)
+                hv[u] = *reinterpret_cast<const u16x8 *>(H + h * CI + slice * 32 +
+                                                          (e / (KR + 4)) * 8);
+        }
+    };
+    if (r0 < r1) load_block(r0);
     for (long long rb = r0; rb < r1; rb += KR) {
         __syncthreads();  // the previous block's fragments have been read
-        // dP rows rb .. rb + 63 (zero from r1 on), 16 chunks of 8 channels per row
-        for (int e = tid; e < KR * 16; e += 256) {
+        // dP^T: row k of the block to column k of channel rows c * 8 .. c * 8 + 7
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int e = tid + 256 * u;
             const int k = e % KR, c = e / KR;
-            const long long r = rb + k;
-            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (r < r1) v = *reinterpret_cast<const u16x8 *>(dP + r * kNnWidth + c * 8);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) pt[(c * 8 + i) * SK + k] = v[i];
+            for (int i = 0; i < 8; ++i) pt[(c * 8 + i) * SK + k] = dv[u][i];
         }
-        // H rows rb - 2 .. rb + 65 (rb >= 2; zero past the last row), 4 chunks of 8 channels of
-        // this slice; row rb - 2 + k goes to position k - tap of tap's copy
-        for (int e = tid; e < (KR + 4) * 4; e += 256) {
-            const int k = e % (KR + 4), c = e / (KR + 4);
-            const long long h = rb - 2 + k;
-            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (h < R) v = *reinterpret_cast<const u16x8 *>(H + h * CI + slice * 32 + c * 8);
+        // H^T: row rb - 2 + k goes to position k - tap of tap's copy
 #pragma unroll
-            for (int t = 0; t < kNnTaps; ++t) {
-                const int kk = k - t;
-                if (kk >= 0 && kk < KR) {
+        for (int u = 0; u < NH; ++u) {
+            const int e = tid + 256 * u;
+            if (e < (KR + 4) * 4) {
+                const int k = e % (KR + 4), c = e / (KR + 4);
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) ht[(t * 32 + c * 8 + i) * SK + kk] = v[i];
+                for (int t = 0; t < kNnTaps; ++t) {
+                    const int kk = k - t;
+                    if (kk >= 0 && kk < KR) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) ht[(t * 32 + c * 8 + i) * SK + kk] = hv[u][i];
+                    }
                 }
             }
         }
+        // the next block's rows are in flight while this one is multiplied
+        if (rb + KR < r1) load_block(rb + KR);
         __syncthreads();
         if (slice == 0 && tid < kNnWidth) {
 #pragma unroll
