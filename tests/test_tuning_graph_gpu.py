@@ -196,6 +196,31 @@ def test_graph_with_8_state_blocks_and_the_persistent_queue(sg):
     ctx.close()
 
 
+def test_block_length_takes_effect_in_eager_calls_and_graphs(sg):
+    # windows of 24..38 positions (copula-n1000) fit three 16-state blocks but not three 8-state
+    # ones: under 8-state blocks the lane kernel hands scenarios to the wave kernel, which shows
+    # that the choice reaches the launch, eager and captured alike; the costs stay exact
+    w = gen.make_workload("copula-n1000", S=4096, threads=ORACLE_THREADS)
+    d = oracle.dist_matrix(w.xy)
+    want = oracle.split(w.tour, d, w.demand, w.Q, threads=ORACLE_THREADS)
+    ctx = fresh_ctx(sg, w.xy)
+    dem = torch.from_numpy(w.demand).cuda()
+    for block, falls_back in ((16, False), (8, True)):
+        ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, 0, 0, 0, block))
+        cost, stats, status = ctx.eval_batch([w.tour], dem, w.Q)
+        assert status == [0]
+        assert np.array_equal(cost.cpu().numpy()[0], want)
+        assert (stats[0].n_fallback > 0) == falls_back, (block, stats[0].n_fallback)
+        g = ctx.graph(1, w.n, dem, w.Q)
+        gcost = g.launch([w.tour])
+        gstats, gstatus = g.stats()
+        assert gstatus == [0]
+        assert np.array_equal(gcost[:1].cpu().numpy()[0], want)
+        assert gstats[0].n_fallback == stats[0].n_fallback, (block, gstats[0].n_fallback)
+        g.close()
+    ctx.close()
+
+
 def test_graph_back_to_back_launches_keep_each_batch(sg, batch):
     # two launches in flight use the two host slots; each batch's result is read after the
     # stream reaches it
