@@ -31,12 +31,15 @@ def _pair(ctx, tour, dem, Q, S):
     return ref_cost, ref, got[:S], st
 
 
-@pytest.mark.parametrize("form", ["auto", "lane", "wave"])
+@pytest.mark.parametrize("form", ["auto", "lane", "lane8", "wave"])
 def test_noalloc_matches_split_eval_on_two_calls_the_second_smaller(sg, form):
     big = gen.make_workload("copula-n1000", S=300_000, threads=16)
     small = gen.make_workload("poisson-n200", S=5000)
     ctx = sg.SplitContext(0)
-    ctx.set_form(form)
+    if form == "lane8":  # 8-state blocks: the copula tour's long windows go to the wave kernel
+        ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, lane_block=8))
+    else:
+        ctx.set_form(form)
     for w in (big, small):
         ctx.set_coords(w.xy)
         dem = torch.from_numpy(w.demand).cuda()
