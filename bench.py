@@ -673,7 +673,8 @@ def main():
                     help="lane form with these launch choices instead of autotuning")
     ap.add_argument("--lane-block", type=int, default=0, choices=[0, 8, 16],
                     help="lane form: states per block of the scenario-per-lane kernel (0: the "
-                         "library default, 16; 8 suits windows shorter than about 24)")
+                         "library default, 16; 8 suits windows shorter than about 24); batch "
+                         "workloads take it with --tuning, else the autotuner chooses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alu-count", action="store_true",
                     help="skip counting the window work that sizes the ALU roofline")
