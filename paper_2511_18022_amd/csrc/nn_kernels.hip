@@ -181,12 +181,9 @@ __global__ __launch_bounds__(256) void nn_features_kernel(NnInstance in, const i
 constexpr int kConvDepth = 2;  // K blocks of activation loads in flight
 
 template <int CI, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nn_conv_kernel(const uint16_t *__restrict__ X,
-                                                      const uint16_t *__restrict__ Wt,
-                                                      const float *__restrict__ bias,
-                                                      const uint16_t *__restrict__ mask,
-                                                      uint16_t *__restrict__ Y, int32_t T,
-                                                      int32_t n)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nn_conv_kernel(
+    const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt, const float *__restrict__ bias,
+    const uint16_t *__restrict__ mask, uint16_t *__restrict__ Y, int32_t T, int32_t n)
 {
     constexpr int K = kNnTaps * CI;
     constexpr int KB = K / 32;
@@ -772,33 +769,40 @@ __global__ __launch_bounds__(256) void nn_dp4_kernel(const float *__restrict__ d
 // R - 2 and input channels 32 s .. 32 s + 31, for every tap and output channel. It stages 64 rows
 // at a time in LDS, transposed so that the contracted index (rows) is contiguous: dP^T [co][k],
 // and one copy of H^T [ci][k] per tap, shifted by the tap, so that every fragment read is an
-// aligned 16-byte load. Wave w accumulates output channels 32 w .. 32 w + 31 for both ci tiles
-// and all taps (20 tiles). Slice 0 also sums the bias gradient, thread co over the staged rows
-// in order.
-template <int CI>
+// aligned 16-byte load. The workgroup's output channels are those of part h = blockIdx.z of
+// 128 / (64 NJ); wave w accumulates NJ 16-channel tiles of them (w NJ 16 ..), for both ci tiles
+// and all taps. Slice 0 also sums the bias gradient, one thread per channel over the staged rows
+// in order. A channel's sums run in the same order for either NJ (layer 1 takes NJ = 1: its
+// single channel slice would otherwise leave half of the compute units idle).
+template <int CI, int NJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nn_wgrad_kernel(
     const uint16_t *__restrict__ H, const uint16_t *__restrict__ dP, long long R, int32_t chunk,
     float *__restrict__ partW, float *__restrict__ partB)
 {
     constexpr int KR = 64;      // rows per staged block
     constexpr int SK = KR + 8;  // bf16 per transposed LDS row (16 bytes of padding)
-    constexpr int NP = KR * 16 / 256;               // dP chunks per thread and block
+    constexpr int CW = 64 * NJ;                     // output channels of the workgroup
+    constexpr int NP = KR * (CW / 8) / 256;         // dP chunks per thread and block
     constexpr int NH = ((KR + 4) * 4 + 255) / 256;  // H chunks per thread and block (at most)
-    __shared__ __attribute__((aligned(16))) uint16_t pt[kNnWidth * SK];
+    static_assert(NJ == 1 || NJ == 2, "one or two output tiles per wavefront");
+    __shared__ __attribute__((aligned(16))) uint16_t pt[CW * SK];
     __shared__ __attribute__((aligned(16))) uint16_t ht[kNnTaps * 32 * SK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
     const int slice = blockIdx.y;
+    const int co0 = blockIdx.z * CW;  // first output channel of the workgroup
     const long long r0 = 2 + (long long)blockIdx.x * chunk;
     const long long r1 = r0 + chunk < R - 2 ? r0 + chunk : R - 2;
-    f32x4 acc[kNnTaps][2][2];
+    f32x4 acc[kNnTaps][2][NJ];
 #pragma unroll
     for (int t = 0; t < kNnTaps; ++t)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) acc[t][i][0] = acc[t][i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[t][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
     // a block's global rows, loaded one block ahead: dP rows rb .. rb + 63 (zero from r1 on),
-    // 16 chunks of 8 channels per row, and H rows rb - 2 .. rb + 65 (rb >= 2; zero past the
+    // CW / 8 chunks of 8 channels per row, and H rows rb - 2 .. rb + 65 (rb >= 2; zero past the
     // last row), 4 chunks of 8 channels of this slice
     u16x8 dv[NP], hv[NH];
     auto load_block = [&](long long rb) {
@@ -808,7 +812,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
             const long long r = rb + e % KR;
             dv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
             if (r < r1)
-                dv[u] = *reinterpret_cast<const u16x8 *>(dP + r * kNnWidth + (e / KR) * 8);
+                dv[u] = *reinterpret_cast<const u16x8 *>(dP + r * kNnWidth + co0 +
+                                                          (e / KR) * 8);
         }
 #pragma unroll
         for (int u = 0; u < NH; ++u) {
@@ -850,7 +855,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
         // the next block's rows are in flight while this one is multiplied
         if (rb + KR < r1) load_block(rb + KR);
         __syncthreads();
-        if (slice == 0 && tid < kNnWidth) {
+        if (slice == 0 && tid < CW) {
 #pragma unroll
             for (int k = 0; k < KR; k += 8) {
                 const u16x8 v = *reinterpret_cast<const u16x8 *>(pt + tid * SK + k);
@@ -861,10 +866,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 #pragma unroll
         for (int kb = 0; kb < KR / 32; ++kb) {
             const int kk = kb * 32 + kq * 8;
-            bf16x8 b[2];
+            bf16x8 b[NJ];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const bf16x8 *>(pt + ((2 * wave + j) * 16 + r16) * SK + kk);
+            for (int j = 0; j < NJ; ++j)
+                b[j] = *reinterpret_cast<const bf16x8 *>(pt + ((NJ * wave + j) * 16 + r16) * SK +
+                                                         kk);
 #pragma unroll
             for (int t = 0; t < kNnTaps; ++t) {
 #pragma unroll
@@ -872,28 +878,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
                     const bf16x8 a =
                         *reinterpret_cast<const bf16x8 *>(ht + (t * 32 + i * 16 + r16) * SK + kk);
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
+                    for (int j = 0; j < NJ; ++j)
                         acc[t][i][j] =
                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[t][i][j], 0, 0, 0);
                 }
             }
         }
     }
-    // lane (r16, kq) holds rows ci = 16 i + 4 kq + q, column co = 16 (2 wave + j) + r16
+    // lane (r16, kq) holds rows ci = 16 i + 4 kq + q, column co = co0 + 16 (NJ wave + j) + r16
     float *dst = partW + (long long)blockIdx.x * (kNnTaps * CI * kNnWidth);
 #pragma unroll
     for (int t = 0; t < kNnTaps; ++t)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < NJ; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int ci = slice * 32 + i * 16 + kq * 4 + q;
-                    const int co = (2 * wave + j) * 16 + r16;
+                    const int co = co0 + (NJ * wave + j) * 16 + r16;
                     dst[((long long)t * CI + ci) * kNnWidth + co] = acc[t][i][j][q];
                 }
-    if (slice == 0 && tid < kNnWidth) partB[(long long)blockIdx.x * kNnWidth + tid] = bsum;
+    if (slice == 0 && tid < CW) partB[(long long)blockIdx.x * kNnWidth + co0 + tid] = bsum;
 }
 
 // sum_{k < chunks} p[k * stride] in chunk order, with the loads of 64 chunks issued before
@@ -1284,11 +1290,13 @@ hipError_t nn_launch_wgrad(int ci, const uint16_t *H, const uint16_t *dP, int32_
 {
     if (chunks != nn_wgrad_chunks(T, n, chunk)) return hipErrorInvalidValue;
     const long long R = (long long)T * (n + 4);
-    const dim3 g(chunks, ci / 32), b(256);
+    const dim3 b(256);
     if (ci == kNnCi0)
-        hipLaunchKernelGGL(nn_wgrad_kernel<kNnCi0>, g, b, 0, st, H, dP, R, chunk, partW, partB);
+        hipLaunchKernelGGL((nn_wgrad_kernel<kNnCi0, 1>), dim3(chunks, 1, 2), b, 0, st, H, dP, R,
+                           chunk, partW, partB);
     else if (ci == kNnWidth)
-        hipLaunchKernelGGL(nn_wgrad_kernel<kNnWidth>, g, b, 0, st, H, dP, R, chunk, partW, partB);
+        hipLaunchKernelGGL((nn_wgrad_kernel<kNnWidth, 2>), dim3(chunks, kNnWidth / 32, 1), b, 0,
+                           st, H, dP, R, chunk, partW, partB);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
