@@ -108,6 +108,10 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build it with `python -m paper_2511_18022_amd._build` "
             "(hipcc, gfx950); there is no CPU fallback")
+    # torch carries its own HIP runtime under the soname this library links against. Loaded
+    # first, it is the one the library binds to; loaded after the library, it would be a second
+    # runtime in the process, and device calls would fail in one of the two.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.split_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
