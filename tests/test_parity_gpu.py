@@ -250,7 +250,7 @@ def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi)
     check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
 
 
-@pytest.mark.parametrize("form", ["auto", "lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["auto", "lane", "lane8", "wave", "mask"])
 @pytest.mark.parametrize("Q", [16384, 20000, 32767, 40000, 2**31 - 1])
 def test_capacity_beyond_16bit_lane_bound(ctx, form, Q):
     # Eq. (2) holds for any capacity. Demands span the whole int16 range up to Q, so windows run
@@ -270,7 +270,7 @@ def test_capacity_beyond_16bit_lane_bound(ctx, form, Q):
     check_against_oracle(ctx, tour, dem, Q, d, form=form, xy=xy)
 
 
-@pytest.mark.parametrize("form", ["lane", "wave", "mask"])
+@pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 def test_negative_demand_reported_at_capacity_beyond_int16(ctx, form):
     # with Q >= 2^15 a negative int16 demand read as unsigned would fit the capacity: it must
     # still be reported as infeasible
