@@ -586,10 +586,31 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
     }
 }
 
+// Issue priority by progress through the work item: 3 over the first quarter of its blocks,
+// down to 0 over the last. Among waves of equal priority a SIMD issues from the oldest, which
+// drives the items of its two wavefronts half an item apart, so that at the end of a launch one
+// of them runs alone for about half an item. Favouring the wavefront that is less far along
+// keeps the two in step (measured on one tour: the two last items of a SIMD end about 14 us
+// apart instead of 57, and the launch takes about 1% less). Used only when every item has the
+// same length (one tour): in a batch of uneven tours the items' ends are spread anyway, and
+// this order measured about 0.5-0.9% slower there.
+__device__ __forceinline__ void item_priority(int c, int nb)
+{
+    const int x = 4 * c, m = nb + 1;
+    if (x < m)
+        __builtin_amdgcn_s_setprio(3);
+    else if (x < 2 * m)
+        __builtin_amdgcn_s_setprio(2);
+    else if (x < 3 * m)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
 // One work item: the 64 scenarios sb*64 .. sb*64+63 of tour t.
 template <int LB>
 __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, long long sb,
-                                          __amdgpu_buffer_rsrc_t rsrc)
+                                          __amdgpu_buffer_rsrc_t rsrc, bool by_progress)
 {
     const int lane = threadIdx.x;
     const long long nscen = a.S;
@@ -640,6 +661,7 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
     // block b's demands live in q[A, B, C, D][b & 3], its starts and weights in [A, B][b & 1];
     // 64 / LB steps per iteration keep these roles and the LDS rows of every step constant
     for (int c = 0; c <= nb; c += LaneCfg<LB>::kSteps) {
+        if (by_progress) item_priority(c, nb);
         lane_step<LB, 0>(L, lane, c, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qB, qD, sA, sB, wA, wB, st);
         lane_step<LB, 1>(L, lane, c + 1, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qC, qA, sB, sA, wB, wA, st);
         lane_step<LB, 2>(L, lane, c + 2, n, QQ, rsrc, wrsrc, rowoff, lane_off, w, qD, qB, sA, sB, wA, wB, st);
@@ -652,6 +674,7 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
         }
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // counts exact only while 8 * max(q) + Q < 2^15 (qor >= max(q)); bit 15 (a negative
     // int16 demand) also lands here, and the general kernel reports it
     st.ovf |= 8u * ((st.qor | (st.qor >> 16)) & 0xFFFFu) + (uint32_t)Q > 32767u;
@@ -683,7 +706,8 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.demand, (short)0, (int)a.lane_bytes, 0x00020000);
     const long long nsb = (a.S + 63) / 64;
-    const long long items = nsb * *(ci64 *)a.tour.nt;
+    const long long ntours = *(ci64 *)a.tour.nt;
+    const long long items = nsb * ntours;
     const bool queue = (long long)gridDim.x < items;
     uint32_t k = blockIdx.x;
     while ((long long)k < items) {
@@ -693,7 +717,7 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
         }
         const long long r = (long long)k / nsb;
         const int t = ((ci32 *)a.tour.order)[r];
-        lane_item<LB>(L, a, t, (long long)k - r * nsb, rsrc);
+        lane_item<LB>(L, a, t, (long long)k - r * nsb, rsrc, ntours == 1);
         k = __builtin_amdgcn_readfirstlane(knext);
     }
 }
