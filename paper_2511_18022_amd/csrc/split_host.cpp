@@ -38,6 +38,7 @@ constexpr int32_t kLaneMaxQ = 16383;
 constexpr int kMaxTimingPairs = 4096;
 constexpr int kGraphSlots = 2;          // a graph's launches alternate between two host slots
 constexpr int32_t kMaxLanePerCu = 8;    // the lane kernel's LDS allows 8 workgroups per CU
+constexpr int32_t kLaneStaticPerCu = kMaxLanePerCu;  // fixed-stride grid: all resident at once
 
 // Device buffers of one evaluation sequence. The context's grow with its calls; a graph owns
 // a fixed set.
@@ -97,6 +98,7 @@ struct BatchInfo {
 struct Plan {
     int form = SPLIT_FORM_LANE;
     int32_t lane_grid = 0, wave_grid = 0, maxn = 0, lane_block = 16;
+    bool lane_static = false;
     uint32_t lane_bytes = 0;
 };
 
@@ -460,8 +462,16 @@ Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t 
     p.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
     if (p.form == SPLIT_FORM_LANE && !lane_addressable) p.form = SPLIT_FORM_WAVE;
     const int64_t items = (S + 63) / 64 * T_grid;
-    const int64_t lg = tu.lane_per_cu <= 0 ? items : (int64_t)ctx->cus * tu.lane_per_cu;
+    // The library's choice (lane_per_cu 0): over one tour, whose items all have the same
+    // length, kLaneStaticPerCu resident workgroups per compute unit taking items at a fixed
+    // stride (no dispatch gap between items, no queue); over a batch of uneven tours, one
+    // workgroup per item.
+    const bool lib_choice = tu.lane_per_cu <= 0;
+    const int64_t lg = !lib_choice     ? (int64_t)ctx->cus * tu.lane_per_cu
+                       : T_grid == 1 ? (int64_t)ctx->cus * kLaneStaticPerCu
+                                     : items;
     p.lane_grid = (int32_t)(lg < items ? lg : items);
+    p.lane_static = lib_choice && T_grid == 1;
     p.lane_block = tu.lane_block == 8 ? 8 : 16;
     p.wave_grid = tu.wave_grid > 0 ? tu.wave_grid : 65536;
     p.maxn = maxn;
@@ -509,6 +519,7 @@ split_status enqueue_kernels(split_ctx *ctx, const Instance &in, const EvalBuffe
     ea.ctl = b.d_ctl;
     ea.lane_bytes = p.lane_bytes;
     ea.lane_grid = p.lane_grid;
+    ea.lane_static = p.lane_static ? 1 : 0;
     ea.lane_block = p.lane_block;
     ea.wave_grid = p.wave_grid;
     ea.maxn = p.maxn;

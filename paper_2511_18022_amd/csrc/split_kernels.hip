@@ -693,9 +693,9 @@ __device__ __forceinline__ void lane_item(LaneLds &L, const EvalArgs &a, int t, 
 }
 
 // Work item k = (tour order[k / nsb], scenario block k % nsb), nsb = ceil(S / 64). Workgroup b
-// runs item b, then takes items gridDim.x, gridDim.x + 1, ... from a queue until none is left
-// (a grid of at least T * nsb workgroups runs one item each and never touches the queue). The
-// next item's index is fetched while the current one runs.
+// runs item b, then either items b + gridDim.x, b + 2 gridDim.x, ... (lane_static) or items
+// gridDim.x, gridDim.x + 1, ... taken from a queue until none is left (a grid of at least
+// T * nsb workgroups runs one item each). A queue index is fetched while the current item runs.
 template <int LB>
 __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
 {
@@ -713,7 +713,10 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
     while ((long long)k < items) {
         uint32_t knext = 0xFFFFFFFFu;
         if (queue) {
-            if (lane == 0) knext = gridDim.x + atomicAdd(&a.ctl->head, 1u);
+            if (a.lane_static)
+                knext = k + gridDim.x;
+            else if (lane == 0)
+                knext = gridDim.x + atomicAdd(&a.ctl->head, 1u);
         }
         const long long r = (long long)k / nsb;
         const int t = ((ci32 *)a.tour.order)[r];
