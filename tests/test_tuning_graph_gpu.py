@@ -332,3 +332,33 @@ def test_graph_at_full_size_in_the_timed_configuration(sg):
     assert est.sum == int(exp.astype(np.int64).sum())
     ctx.close()
 
+
+
+@pytest.mark.parametrize("block", [16, 8])
+def test_fixed_stride_grid_with_ragged_items(sg, block):
+    # One tour over more work items than the default one-tour grid of 8 workgroups per compute
+    # unit: 150,001 scenarios are 2344 items (the last holds one scenario), so the first
+    # workgroups take a second item at the fixed stride and the others one. Eager calls, a
+    # captured graph and the allocation-free call all against the oracle on every scenario.
+    w = gen.make_workload("copula-n1000", S=150_001, threads=ORACLE_THREADS)
+    tour = np.ascontiguousarray(w.tour[:300])
+    ctx = fresh_ctx(sg, w.xy)
+    ctx.set_tuning(sg.SplitTuning(sg.FORM_LANE, lane_block=block))
+    dem = torch.from_numpy(w.demand).cuda()
+    want = oracle.split(tour, oracle.dist_matrix(w.xy), w.demand, w.Q, threads=ORACLE_THREADS)
+    print(f"[stride] lane_block {block}: n=300 S={w.S}", flush=True)
+    eager, est = ctx.eval(tour, dem, w.Q)
+    assert np.array_equal(eager.cpu().numpy(), want)
+    assert est.sum == int(want.astype(np.int64).sum())
+    g = ctx.graph(1, len(tour), dem, w.Q)
+    for rep in range(2):
+        got = g.launch([tour])
+        torch.cuda.synchronize()
+        assert np.array_equal(got[0].cpu().numpy(), want), f"replay {rep}"
+        ctx.eval(tour[:100], dem, w.Q)  # eager work between replays
+    g.close()
+    cost = torch.full((w.S,), -1, dtype=torch.int32, device="cuda")
+    st = ctx.eval_noalloc(tour, dem, w.Q, cost)
+    assert np.array_equal(cost.cpu().numpy(), want)
+    assert (st.sum, st.var) == (est.sum, est.var)
+    ctx.close()
