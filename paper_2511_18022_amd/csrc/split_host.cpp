@@ -39,6 +39,7 @@ constexpr int kMaxTimingPairs = 4096;
 constexpr int kGraphSlots = 2;          // a graph's launches alternate between two host slots
 constexpr int32_t kMaxLanePerCu = 8;    // the lane kernel's LDS allows 8 workgroups per CU
 constexpr int32_t kLaneStaticPerCu = kMaxLanePerCu;  // fixed-stride grid: all resident at once
+constexpr int64_t kLaneStaticMaxRounds = 8;          // and at most this many items each
 
 // Device buffers of one evaluation sequence. The context's grow with its calls; a graph owns
 // a fixed set.
@@ -90,7 +91,7 @@ StageLayout stage_layout(int32_t capT, int64_t cap_n)
 
 // Summary of a validated batch.
 struct BatchInfo {
-    int32_t T = 0, max_id = 0, maxn = 0;
+    int32_t T = 0, max_id = 0, maxn = 0, minn = 0;
     int64_t total_n = 0;
 };
 
@@ -98,7 +99,7 @@ struct BatchInfo {
 struct Plan {
     int form = SPLIT_FORM_LANE;
     int32_t lane_grid = 0, wave_grid = 0, maxn = 0, lane_block = 16;
-    bool lane_static = false;
+    bool lane_static = false, lane_uniform = false;
     uint32_t lane_bytes = 0;
 };
 
@@ -404,6 +405,7 @@ split_status check_tours(split_ctx *ctx, const char *who, const Instance &in,
                         (long long)n64);
         const int32_t n = (int32_t)n64;
         bi.maxn = n > bi.maxn ? n : bi.maxn;
+        bi.minn = (t == 0 || n < bi.minn) ? n : bi.minn;
         const int32_t *tour = tours + tour_ptr[t];
         for (int32_t k = 0; k < n; ++k) {
             const int32_t c = tour[k];
@@ -447,9 +449,10 @@ void stage_write(char *h, const StageLayout &L, const int32_t *tours, const int6
     memcpy(h + L.off_tours, tours, sizeof(int32_t) * (size_t)tour_ptr[T]);
 }
 
-// Launch configuration from the tuning. T_grid bounds T; maxn and max_id bound the tours.
+// Launch configuration from the tuning. T_grid bounds T; maxn and max_id bound the tours;
+// `uniform`: every tour of the launch has the same length (so has every work item).
 Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t ld, int32_t Q,
-               int32_t T_grid, int32_t maxn, int32_t max_id)
+               int32_t T_grid, int32_t maxn, int32_t max_id, bool uniform)
 {
     Plan p;
     p.form = tu.form;
@@ -462,16 +465,18 @@ Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t 
     p.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
     if (p.form == SPLIT_FORM_LANE && !lane_addressable) p.form = SPLIT_FORM_WAVE;
     const int64_t items = (S + 63) / 64 * T_grid;
-    // The library's choice (lane_per_cu 0): over one tour, whose items all have the same
-    // length, kLaneStaticPerCu resident workgroups per compute unit taking items at a fixed
-    // stride (no dispatch gap between items, no queue); over a batch of uneven tours, one
-    // workgroup per item.
+    // The library's choice (lane_per_cu 0): when every item has the same length (one tour, or
+    // tours of one length) and there are at most kLaneStaticMaxRounds items per workgroup,
+    // kLaneStaticPerCu resident workgroups per compute unit taking items at a fixed stride (no
+    // dispatch gap between items, no queue). Otherwise one workgroup per item: with many items
+    // per workgroup a fixed split's imbalance grows (measured: 8 items each gain 1%, 32 lose 3%).
     const bool lib_choice = tu.lane_per_cu <= 0;
-    const int64_t lg = !lib_choice     ? (int64_t)ctx->cus * tu.lane_per_cu
-                       : T_grid == 1 ? (int64_t)ctx->cus * kLaneStaticPerCu
-                                     : items;
+    const int64_t sgrid = (int64_t)ctx->cus * kLaneStaticPerCu;
+    const bool fixed = lib_choice && uniform && items <= sgrid * kLaneStaticMaxRounds;
+    const int64_t lg = !lib_choice ? (int64_t)ctx->cus * tu.lane_per_cu : fixed ? sgrid : items;
     p.lane_grid = (int32_t)(lg < items ? lg : items);
-    p.lane_static = lib_choice && T_grid == 1;
+    p.lane_static = fixed;
+    p.lane_uniform = uniform;
     p.lane_block = tu.lane_block == 8 ? 8 : 16;
     p.wave_grid = tu.wave_grid > 0 ? tu.wave_grid : 65536;
     p.maxn = maxn;
@@ -520,6 +525,7 @@ split_status enqueue_kernels(split_ctx *ctx, const Instance &in, const EvalBuffe
     ea.lane_bytes = p.lane_bytes;
     ea.lane_grid = p.lane_grid;
     ea.lane_static = p.lane_static ? 1 : 0;
+    ea.lane_uniform = p.lane_uniform ? 1 : 0;
     ea.lane_block = p.lane_block;
     ea.wave_grid = p.wave_grid;
     ea.maxn = p.maxn;
@@ -591,7 +597,8 @@ split_status eval_batch(split_ctx *ctx, const char *who, const int32_t *tours,
     HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[slot], stream));
     ctx->stage_ev_used[slot] = true;
 
-    const Plan p = make_plan(ctx, ctx->tuning, S, ld, Q, T, bi.maxn, bi.max_id);
+    const Plan p = make_plan(ctx, ctx->tuning, S, ld, Q, T, bi.maxn, bi.max_id,
+                             bi.minn == bi.maxn);
     if (p.form == SPLIT_FORM_MASK && (__int128)ctx->buf.cap_pos * S > ctx->buf.cap_mask) {
         // one int16 window start per (position row, scenario)
         HIP_TRY(ctx, hipDeviceSynchronize());
@@ -861,7 +868,7 @@ split_status split_eval_noalloc(split_ctx *ctx, const int32_t *tour, int32_t n,
                                 hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(b.d_stage + L.off_tours, tour, sizeof(int32_t) * (size_t)n,
                                 hipMemcpyHostToDevice, stream));
-    const Plan p = make_plan(ctx, tu, S, ld, Q, 1, bi.maxn, bi.max_id);
+    const Plan p = make_plan(ctx, tu, S, ld, Q, 1, bi.maxn, bi.max_id, true);
     // the prep kernel zeroes the result block and the counters of every call
     st = enqueue_kernels(ctx, ctx->inst, b, L, p, demand, S, ld, Q, cost, S, stream, false);
     if (st != SPLIT_OK) return st;
@@ -1016,7 +1023,7 @@ split_status split_autotune(split_ctx *ctx, const int32_t *tours, const int64_t 
     split_tuning win = saved;
     double win_ms = 1e300;
     const Plan lane_probe = make_plan(ctx, split_tuning{SPLIT_FORM_LANE, 0, 0, 0, 0}, S, ld, Q,
-                                      T, bi.maxn, bi.max_id);
+                                      T, bi.maxn, bi.max_id, bi.minn == bi.maxn);
     if (lane_probe.form == SPLIT_FORM_LANE) {
         // the block length first (it follows the window lengths, so the demand law), then the
         // grid and the order with that block length. 8-state blocks hand windows longer than
@@ -1220,7 +1227,8 @@ split_status split_graph_create(split_ctx *ctx, int32_t max_T, int64_t max_total
                         (int64_t)nblk * max_T, true);
     if (st != SPLIT_OK) return bail(st);
     // any tour of the instance: lengths up to N, ids up to N
-    gr->plan = make_plan(ctx, ctx->tuning, S, ld, Q, max_T, N, N);
+    // the tours of a replay are known only then: a fixed item stride only for one tour
+    gr->plan = make_plan(ctx, ctx->tuning, S, ld, Q, max_T, N, N, max_T == 1);
     if (gr->plan.form == SPLIT_FORM_MASK)
         return bail(fail(ctx, SPLIT_E_INVAL, "split_graph_create: the two-kernel form is an "
                          "ablation and is not captured"));

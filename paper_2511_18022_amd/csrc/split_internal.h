@@ -106,6 +106,7 @@ struct EvalArgs {
     int32_t lane_grid;       // lane kernel workgroups (>= the work items: one item each)
     int32_t lane_static;     // lane kernel, fewer workgroups than items: 1 = each takes items
                              // at a fixed stride of lane_grid, 0 = from the queue
+    int32_t lane_uniform;    // lane kernel: 1 = every tour of the launch has the same length
     int32_t lane_block;      // lane kernel block length: 16 or 8 states
     int32_t wave_grid;       // wave kernel workgroups of a full evaluation (form wave)
     int32_t maxn;            // bound on the tour lengths (sizes the wave kernel's LDS)

@@ -592,8 +592,8 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
 // of them runs alone for about half an item. Favouring the wavefront that is less far along
 // keeps the two in step (measured on one tour: the two last items of a SIMD end about 14 us
 // apart instead of 57, and the launch takes about 1% less). Used only when every item has the
-// same length (one tour): in a batch of uneven tours the items' ends are spread anyway, and
-// this order measured about 0.5-0.9% slower there.
+// same length (one tour, or tours of one length): in a batch of uneven tours the items' ends
+// are spread anyway, and this order measured about 0.5-0.9% slower there.
 __device__ __forceinline__ void item_priority(int c, int nb)
 {
     const int x = 4 * c, m = nb + 1;
@@ -706,8 +706,7 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)a.demand, (short)0, (int)a.lane_bytes, 0x00020000);
     const long long nsb = (a.S + 63) / 64;
-    const long long ntours = *(ci64 *)a.tour.nt;
-    const long long items = nsb * ntours;
+    const long long items = nsb * *(ci64 *)a.tour.nt;
     const bool queue = (long long)gridDim.x < items;
     uint32_t k = blockIdx.x;
     while ((long long)k < items) {
@@ -720,7 +719,7 @@ __global__ __launch_bounds__(64) void split_lane_kernel(EvalArgs a)
         }
         const long long r = (long long)k / nsb;
         const int t = ((ci32 *)a.tour.order)[r];
-        lane_item<LB>(L, a, t, (long long)k - r * nsb, rsrc, ntours == 1);
+        lane_item<LB>(L, a, t, (long long)k - r * nsb, rsrc, a.lane_uniform != 0);
         k = __builtin_amdgcn_readfirstlane(knext);
     }
 }
