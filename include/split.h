@@ -191,12 +191,11 @@ split_status split_set_form(split_ctx *ctx, int form);
  * Section 3's Eqs. (1)-(3)).
  *  form         split_form; SPLIT_FORM_AUTO takes the wave form for short tours over few
  *               scenarios (see split_form), else the lane form.
- *  lane_per_cu  lane form: 0 = the library's choice: when every tour of the call has the
- *               same length (one tour, say) and the work items (a tour and 64 of its
- *               scenarios) are at most 8 per workgroup, 8 persistent workgroups per compute
- *               unit, each taking work items at a fixed stride; otherwise (and in graphs of
- *               more than one tour) one workgroup per work item. 1..8 = that many persistent
- *               workgroups per compute unit, taking work items from a queue.
+ *  lane_per_cu  lane form: 0 = the library's choice: over one tour whose work items (64 of
+ *               its scenarios each) are at most 16 per workgroup, 8 persistent workgroups per
+ *               compute unit, each taking work items at a fixed stride; otherwise one
+ *               workgroup per work item. 1..8 = that many persistent workgroups per compute
+ *               unit, taking work items from a queue.
  *  order        lane form: 0 = work items of longer tours first, 1 = tours in the given order.
  *  wave_grid    wave form: workgroups of the launch; 0 = min(T * S, 65536).
  *  lane_block   lane form: states per block of the scenario-per-lane kernel, 0 or 16 = 16,

@@ -39,7 +39,7 @@ constexpr int kMaxTimingPairs = 4096;
 constexpr int kGraphSlots = 2;          // a graph's launches alternate between two host slots
 constexpr int32_t kMaxLanePerCu = 8;    // the lane kernel's LDS allows 8 workgroups per CU
 constexpr int32_t kLaneStaticPerCu = kMaxLanePerCu;  // fixed-stride grid: all resident at once
-constexpr int64_t kLaneStaticMaxRounds = 8;          // and at most this many items each
+constexpr int64_t kLaneStaticMaxRounds = 16;         // and at most this many items each
 
 // Device buffers of one evaluation sequence. The context's grow with its calls; a graph owns
 // a fixed set.
@@ -465,14 +465,14 @@ Plan make_plan(const split_ctx *ctx, const split_tuning &tu, int64_t S, int64_t 
     p.lane_bytes = lane_addressable ? (uint32_t)lane_bytes : 0u;
     if (p.form == SPLIT_FORM_LANE && !lane_addressable) p.form = SPLIT_FORM_WAVE;
     const int64_t items = (S + 63) / 64 * T_grid;
-    // The library's choice (lane_per_cu 0): when every item has the same length (one tour, or
-    // tours of one length) and there are at most kLaneStaticMaxRounds items per workgroup,
-    // kLaneStaticPerCu resident workgroups per compute unit taking items at a fixed stride (no
-    // dispatch gap between items, no queue). Otherwise one workgroup per item: with many items
-    // per workgroup a fixed split's imbalance grows (measured: 8 items each gain 1%, 32 lose 3%).
+    // The library's choice (lane_per_cu 0): over one tour with at most kLaneStaticMaxRounds
+    // items per workgroup, kLaneStaticPerCu resident workgroups per compute unit taking items
+    // at a fixed stride (no dispatch gap between items, no queue); otherwise one workgroup per
+    // item. Measured: 8, 12 and 16 items per workgroup of one tour gain about 1%; over several
+    // tours, even of one length, their items differ enough that a fixed split lost 2-3%.
     const bool lib_choice = tu.lane_per_cu <= 0;
     const int64_t sgrid = (int64_t)ctx->cus * kLaneStaticPerCu;
-    const bool fixed = lib_choice && uniform && items <= sgrid * kLaneStaticMaxRounds;
+    const bool fixed = lib_choice && T_grid == 1 && items <= sgrid * kLaneStaticMaxRounds;
     const int64_t lg = !lib_choice ? (int64_t)ctx->cus * tu.lane_per_cu : fixed ? sgrid : items;
     p.lane_grid = (int32_t)(lg < items ? lg : items);
     p.lane_static = fixed;
