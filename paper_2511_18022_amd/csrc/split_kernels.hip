@@ -53,7 +53,8 @@ __device__ __forceinline__ int32_t arc_cost(const PrepArgs &a, int u, int v)
 // past the call's T return at once.
 __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 {
-    __shared__ long long red[1024];
+    __shared__ long long red[16];
+    __shared__ int32_t ends[2];  // c(0, first customer), c(last customer, 0)
     const int tid = threadIdx.x;
     const int t = blockIdx.x;
     if (t >= *a.tour.nt) return;
@@ -68,6 +69,9 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
         const int sk = tour[k - 1];
         rowoff[k] = (long long)(sk - 1) * a.ld * (long long)sizeof(uint16_t);
         rowoff32[k] = (uint32_t)rowoff[k];
+        // the two depot arcs of w_0 and w_n, from the threads that hold their customers
+        if (k == 1) ends[0] = arc_cost(a, 0, sk);
+        if (k == n) ends[1] = arc_cost(a, sk, 0);
         if (k < n) {
             const int sn = tour[k];
             const int link = arc_cost(a, sk, sn);
@@ -75,11 +79,13 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
             w[k] = arc_cost(a, sk, 0) + arc_cost(a, 0, sn) - link;
         }
     }
-    red[tid] = link_sum;
+    // sum of the links: within each wavefront, then over the 16 wavefronts (integers: the
+    // order does not change the result)
+    for (int off = 32; off > 0; off >>= 1) link_sum += __shfl_xor(link_sum, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = link_sum;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
+    if (tid == 0) {
+        for (int i = 1; i < 16; ++i) red[0] += red[i];
     }
     // positions n+1 .. n+kRowPad: row 0 (valid memory), absent for the lane kernel, weight 0,
     // so that kernels can load whole blocks of positions past n without guards
@@ -91,8 +97,8 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
     if (tid == 0) {
         rowoff[0] = 0;
         rowoff32[0] = kRowAbsent;
-        w[0] = arc_cost(a, 0, tour[0]);
-        w[n] = (int32_t)(red[0] + arc_cost(a, tour[n - 1], 0));
+        w[0] = ends[0];
+        w[n] = (int32_t)(red[0] + ends[1]);
         DevStats *st = a.stats + t;
         st->sum = 0;
         st->sq_lo = 0;
