@@ -128,7 +128,7 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 //   dl  : suffix minima of g inside each block of the last 64 positions, as 16-bit offsets
 //         from the block minimum (row = position & 63);
 //   pp  : prefix loads P mod 2^16 of the last 64 positions, positions (2k, 2k+1) in dword row
-//         k & 31; rows 0 .. kMirror-1 repeated after the ring so that a 6-row read never wraps.
+//         k & 31; rows 0 .. kMirror-1 repeated after the ring so that an 8-row read never wraps.
 // The window minimum of a state of block c whose window starts at s in an older block b is
 //   min(rec[b].bm + dl[s], rec[b].bs, minimum of g over block c before the state).
 // Window starts advance by counting expired positions as packed 16-bit differences: the two
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 // unrolled 64 / LB times so that every LDS store has a constant offset.
 
 constexpr int kRingPairs = 32;  // prefix-load ring of 64 positions, two per dword
-constexpr int kMirror = 5;      // ring rows repeated after the ring
+constexpr int kMirror = 7;      // ring rows repeated after the ring
 
 // Blocks of LB states: kSteps = blocks in the 64-position history (the unroll of the block
 // loop), kLog = log2(LB). The ring, the suffix offsets and the four block records hold every
@@ -366,6 +366,58 @@ __device__ __forceinline__ void lane_starts_pairs(LaneLds &L, int lane, int firs
         lane_starts_careful<LB>(L, lane, first, TT, S_in, sOut);
 }
 
+// 16 positions (8 packed dwords) from the even position below Sp.
+struct WideData {
+    uint32_t d[8];
+    int base;
+};
+__device__ __forceinline__ WideData wide_read(LaneLds &L, uint32_t lane4, int Sp)
+{
+    WideData p;
+    const uint32_t off = ((uint32_t)Sp & 0x1F00u) | lane4;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) p.d[r] = pp_at(L, off, r);
+    p.base = Sp & ~0x80;
+    return p;
+}
+template <int D>
+__device__ __forceinline__ int wide_count(const WideData &p, uint32_t T, uint32_t &last)
+{
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < D; r += 2) {
+        const uint32_t x = sign_bytes(pk_sub16(p.d[r + 1], T), pk_sub16(p.d[r], T));
+        cnt = __builtin_popcount(x) + cnt;
+        last = x;
+    }
+    return p.base + (int)(cnt << 4);
+}
+// Redo of a block's starts after the fast counts fell short or read past the written prefix
+// loads: pairs again, from one 16-position read each, the first state counting 12 positions and
+// the second all 16 (half the serial reads of a state-by-state redo, which has no other work
+// left to overlap); where those fall short or read past the written prefix loads too, state by
+// state. Used for 16-state blocks (an 8-state block's ring rarely holds 16 positions ahead).
+template <int LB>
+__device__ __forceinline__ void lane_starts_wide(LaneLds &L, int lane, int first,
+                                                 const uint32_t (&TT)[LB / 2], int Sp,
+                                                 int (&sOut)[LB])
+{
+    const uint32_t lane4 = (uint32_t)lane << 2;
+    const int S_in = Sp;
+    uint32_t sat = 0;
+#pragma unroll
+    for (int u = 0; u < LB / 2; ++u) {
+        const WideData p = wide_read(L, lane4, Sp);
+        uint32_t x0, x1;
+        sOut[2 * u] = wide_count<6>(p, TT[u] & 0xFFFFu, x0);
+        sOut[2 * u + 1] = wide_count<8>(p, TT[u] >> 16, x1);
+        sat |= x0 | x1;
+        Sp = sOut[2 * u + 1];
+    }
+    if (__any((int32_t)sat < 0 || (s_of(sOut[LB - 3]) & ~1) > first + LB - 16))
+        lane_starts_careful<LB>(L, lane, first, TT, S_in, sOut);
+}
+
 // g of state t of a block (t uniform). Written as explicit selects: the compiler would
 // otherwise turn it into an indexed load from a scratch copy of the whole block.
 template <int LB>
@@ -572,9 +624,14 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
         // g_n = f_n, which need not fit 16 bits)
         if (c < nb) lane_block_end<LB, R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
         // the last pair read positions up to its base + 11; the ring is written up to
-        // first + LB-1. Either condition below is rare: redo the block's starts state by state.
-        if (__any((int32_t)sat < 0 || (s_of(sNext[LB - 3]) & ~1) > first + LB - 12))
-            lane_starts_careful<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
+        // first + LB-1. Either condition below is rare: redo the block's starts (16-state
+        // blocks with wider pair counts first, then state by state where those fall short).
+        if (__any((int32_t)sat < 0 || (s_of(sNext[LB - 3]) & ~1) > first + LB - 12)) {
+            if constexpr (LB == 16)
+                lane_starts_wide<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
+            else
+                lane_starts_careful<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
+        }
         if (c == nb) st.gres = block_g_at<LB>(gb, n & (LB - 1));
         return;
     }

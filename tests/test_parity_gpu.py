@@ -234,10 +234,13 @@ def test_maximum_instance_and_tour_length(ctx):
 
 @pytest.mark.parametrize("form", ["lane", "lane8", "wave", "mask"])
 @pytest.mark.parametrize("Q,lo,hi", [(16383, 4000, 16383), (16383, 1, 16383), (4681, 2000, 4681),
-                                     (3000, 0, 400)])
+                                     (3000, 0, 400), (16000, 0, 2047)])
 def test_large_demands_relative_to_16bit_window_arithmetic(ctx, form, Q, lo, hi):
     # demands close to Q make windows of one or two customers; the prefix-load differences the
-    # lane kernel compares in 16 bits then grow past 2^15 for positions ahead of a state
+    # lane kernel compares in 16 bits then grow past 2^15 for positions ahead of a state. The last
+    # case stays inside the lane kernel's bound (8 * 2047 + 16000 < 2^15) with windows of about
+    # 16 positions, while 12 demands ahead can sum past it: a redo's 16-position counts then
+    # compare differences beyond 2^15
     rng = np.random.default_rng(Q + lo)
     N = 260
     xy = gen.coords(13, N)
