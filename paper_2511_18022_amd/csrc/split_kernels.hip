@@ -133,9 +133,9 @@ __global__ __launch_bounds__(1024) void split_prep_kernel(PrepArgs a)
 //   min(rec[b].bm + dl[s], rec[b].bs, minimum of g over block c before the state).
 // Window starts advance by counting expired positions as packed 16-bit differences: the two
 // states of a pair share one read of 12 positions starting at the even position below the
-// previous start; the first counts 8 of them, the second all 12. A block where some lane's last
-// counted position expired (the count may be short), or where a read reached past the written
-// prefix loads, has its starts redone one state at a time. The counts are exact while
+// previous start; in a fast block the first counts 8 of them and the second 10 (12 elsewhere).
+// A block where some lane's last counted position expired (the count may be short), or where a
+// count reached past the written prefix loads, has its starts redone. The counts are exact while
 // 8 * max(q) + Q < 2^15 (every compared difference then fits a signed 16-bit value).
 // Scenarios the kernel cannot finish exactly (that demand bound broken, a window longer than
 // its history, suffix offsets beyond 16 bits) are queued for the general kernel.
@@ -339,6 +339,19 @@ __device__ __forceinline__ int pair_count(const PairData &p, uint32_t T, uint32_
         cnt = __builtin_popcount(x) + cnt;
         last = x;
     }
+    return p.base + (int)(cnt << 4);
+}
+
+// Start counted over the first 10 positions of a pair's read; last < 0: position 9 expired.
+__device__ __forceinline__ int pair_count10(const PairData &p, uint32_t T, uint32_t &last)
+{
+    const uint32_t x0 = sign_bytes(pk_sub16(p.d[1], T), pk_sub16(p.d[0], T));
+    const uint32_t x1 = sign_bytes(pk_sub16(p.d[3], T), pk_sub16(p.d[2], T));
+    const uint32_t x2 = sign_bytes(pk_sub16(p.d[4], T), 0u);
+    last = x2;
+    uint32_t cnt = __builtin_popcount(x0);
+    cnt = __builtin_popcount(x1) + cnt;
+    cnt = __builtin_popcount(x2) + cnt;
     return p.base + (int)(cnt << 4);
 }
 
@@ -609,7 +622,7 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
             }
             __builtin_amdgcn_sched_barrier(0);
             uint32_t x1;
-            sNext[2 * u + 1] = pair_count<6>(pcur, TT[u] >> 16, x1);
+            sNext[2 * u + 1] = pair_count10(pcur, TT[u] >> 16, x1);
             sat |= x1;
             pprev = pcur;
             if (u + 1 < LB / 2) pcur = pair_read(L, lane4, sNext[2 * u + 1]);
@@ -623,10 +636,10 @@ __device__ __forceinline__ void lane_step(LaneLds &L, int lane, int c, int n, ui
         // no later block reads the last block's records (and its suffix offsets would hold
         // g_n = f_n, which need not fit 16 bits)
         if (c < nb) lane_block_end<LB, R>(L, lane, gb, st.bm1, st.bm2, st.ovf);
-        // the last pair read positions up to its base + 11; the ring is written up to
+        // the last pair counts positions up to its base + 9; the ring is written up to
         // first + LB-1. Either condition below is rare: redo the block's starts (16-state
         // blocks with wider pair counts first, then state by state where those fall short).
-        if (__any((int32_t)sat < 0 || (s_of(sNext[LB - 3]) & ~1) > first + LB - 12)) {
+        if (__any((int32_t)sat < 0 || (s_of(sNext[LB - 3]) & ~1) > first + LB - 10)) {
             if constexpr (LB == 16)
                 lane_starts_wide<LB>(L, lane, first, TT, sCur[LB - 1], sNext);
             else
